@@ -1,0 +1,190 @@
+"""Benchmark of the FFA + boxcar S/N search on one MI355X.
+
+One step = the whole hot path over one batch: FP64 statistics of every
+series, every pseudo-octave downsampled, every FFA transform folded and every
+kept profile's boxcar S/N written (the periodogram). Inputs are resident in
+HBM before the timed region starts.
+
+Workload (default): 512 series of 2^23 samples at 64 us (the paper's
+benchmark shape, Sec. 5.8), N(0,1) noise with 10 % of the series carrying a
+pulse; periods 0.5-10 s, 240-259 bins, 9 boxcar widths (1..48 bins). It is
+run with the series stored as bfloat16 (normalised in FP64 beforehand), the
+headline, and as plain float32 for comparison.
+
+Prints one JSON line (rank 0).
+"""
+import argparse
+import concurrent.futures as cf
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--series", type=int, default=512)
+    ap.add_argument("--log2n", type=int, default=23)
+    ap.add_argument("--variants", default="bf16,f32,f16")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_inputs(torch, nseries, nsamp):
+    import synth
+    x = torch.empty((nseries, nsamp), dtype=torch.float32, device="cuda")
+    pulsed = synth.workload3_pulsed(nseries)
+    def gen(i):
+        s, _ = synth.workload3_series(i, nsamp=nsamp, nseries=nseries, pulsed=pulsed)
+        return i, s
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        for i, s in ex.map(gen, range(nseries)):
+            x[i].copy_(torch.from_numpy(s))
+    torch.cuda.synchronize()
+    return x
+
+
+def lowp(torch, x, dt):
+    # normalised in FP64 per series, then rounded to the storage type (RNE)
+    out = torch.empty(x.shape, dtype=dt, device=x.device)
+    for i in range(x.shape[0]):
+        xd = x[i].double()
+        mu = xd.mean()
+        sd = torch.sqrt(((xd - mu) ** 2).mean())
+        out[i].copy_(((xd - mu) / sd).to(dt))
+    torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(seconds, nsamp):
+    """The FP64 oracle, as it stands, on whole series of the same workload
+    until `seconds` have passed (at least one series)."""
+    import oracle
+    import synth
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    rows = 0
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        x, _ = synth.workload3_series(done, nsamp=nsamp, pulsed=pulsed)
+        pg = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                           cfg.bins_max, cfg.widths)
+        rows += pg.snr.shape[0]
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": rows / dt, "unit": "profiles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} whole series of 2^{int(math.log2(nsamp))} samples, full plan "
+                      f"({rows} profiles x 9 widths) in {dt:.1f} s, FP64 depth-first FFA"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2004_03701_amd as ffa
+    import synth
+
+    nsamp = 1 << a.log2n
+    cfg = synth.workload3_config()
+    x32 = make_inputs(torch, a.series, nsamp)
+    variants = [v for v in a.variants.split(",") if v]
+    store = {"f32": (ffa.FFA_F32, None), "bf16": (ffa.FFA_BF16, torch.bfloat16),
+             "f16": (ffa.FFA_F16, torch.float16)}
+    ctx = ffa.ffa_create(0)
+    results = {}
+    for v in variants:
+        dt_code, tdt = store[v]
+        xs = x32 if tdt is None else lowp(torch, x32, tdt)
+        series = [xs[i] for i in range(a.series)]
+        prm = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                               cfg.bins_max, cfg.widths, normalise=True, dtype=dt_code)
+               for _ in range(a.series)]
+        rows1 = ffa.ffa_plan_rows(prm[0], nsamp)
+        bins = ffa.ffa_plan_export(prm[0], nsamp)["bins"].astype(np.int64)
+        snr = torch.empty((rows1 * a.series, len(cfg.widths)), dtype=torch.float32,
+                          device="cuda")
+        for _ in range(a.warmup):
+            ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
+        torch.cuda.synchronize()
+        ffa.ffa_set_timing(ctx, not a.graph)
+        ffa.ffa_read_timing(ctx, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = ffa.ffa_read_timing(ctx, reset=True)
+        ffa.ffa_set_timing(ctx, False)
+        assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+        ms = 1e3 * wall / a.steps
+        profiles = rows1 * a.series
+        esize = 4 if v == "f32" else 2
+        alg_bytes = a.series * (int(bins.sum()) * esize + rows1 * len(cfg.widths) * 4)
+        fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
+        res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),
+               "profiles": profiles, "alg_bytes_fold": alg_bytes, "timing": tm}
+        if fold_ms:
+            res["fold_ms_per_step"] = fold_ms
+            res["fold_launches_per_step"] = tm["fold_launches"] / a.steps
+            res["fold_alg_GBps"] = alg_bytes / (fold_ms * 1e-3) / 1e9
+            res["stats_ms_per_step"] = tm["stats_ms"] / a.steps
+            res["downsample_ms_per_step"] = tm["downsample_ms"] / a.steps
+        results[v] = res
+        del series, xs, snr
+        torch.cuda.empty_cache()
+    head = variants[0]
+    r = results[head]
+    out = {
+        "metric": "trial profiles/sec and HBM GB/s (FFA+S/N), batched BF16 vs plain FP32, 1 GPU",
+        "value": r["profiles_per_s"],
+        "unit": "profiles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.series} series x 2^{a.log2n} samples at 64 us, periods "
+                               f"0.5-10 s, bins 240-259, widths 1-48 (9), storage {head}",
+                   "storage": head, "series": a.series, "nsamp": nsamp,
+                   "graph": bool(a.graph)},
+    }
+    if "fold_alg_GBps" in r:
+        ach = r["fold_alg_GBps"]
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "timing"}
+                       for k, v in results.items()}
+    if "f32" in results and head != "f32":
+        out["speedup_vs_f32"] = results[head]["profiles_per_s"] / results["f32"]["profiles_per_s"]
+    if a.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds, nsamp)
+    ffa.ffa_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

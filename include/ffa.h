@@ -1,0 +1,212 @@
+/*
+ * ffa.h -- C ABI of the MI355X FFA periodicity search.
+ *
+ * The library computes the hot path of the search described by Morello,
+ * Barr, Stappers, Keane & Lyne (2020), "Optimal periodicity searching:
+ * revisiting the Fast Folding Algorithm for large-scale pulsar surveys":
+ * normalise a time series (Sec. 5.2), downsample it for every pseudo-octave
+ * of a period range (Sec. 5.3), fold it at every trial period with the FFA
+ * (Sec. 2), and evaluate the boxcar matched-filter S/N of every folded
+ * profile (Sec. 5.4), giving the two-dimensional periodogram of Sec. 5.5.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an ffa_status: FFA_OK (0) or a negative error code.
+ *     No C++ exception crosses the ABI.
+ *   - Arguments are validated before any device work is queued; on error
+ *     nothing is written except the context's last-error message.
+ *   - Pointers documented as DEVICE point to memory on the context's GPU
+ *     (for instance torch tensor storage); HOST pointers point to host memory.
+ *     The caller owns every buffer passed in; the context owns its workspace.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Device work is
+ *     queued on it asynchronously: device outputs are valid once the stream
+ *     has synchronised. Host outputs are written before the call returns.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef FFA_MI355X_H
+#define FFA_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFA_OK = 0,
+  FFA_ERR_INVALID_ARG = -1,      /* a null pointer, a size or a parameter out of its domain */
+  FFA_ERR_RANGE = -2,            /* period_min / (bins_min * tsamp) < 1, or no transform with m >= 2 */
+  FFA_ERR_BUFFER_TOO_SMALL = -3, /* capacity below the number of periodogram rows */
+  FFA_ERR_NOMEM = -4,            /* device or host allocation failed */
+  FFA_ERR_DEVICE = -5,           /* a HIP runtime call failed */
+  FFA_ERR_DEGENERATE = -6,       /* zero or non-finite variance of a series to normalise */
+  FFA_ERR_NOT_IMPLEMENTED = -7
+} ffa_status;
+
+/* Storage type of an input series. Arithmetic is FP32 (FP64 for the
+ * normalisation statistics and the S/N noise constants) whatever the storage. */
+typedef enum { FFA_F32 = 0, FFA_BF16 = 1, FFA_F16 = 2 } ffa_dtype;
+
+typedef struct ffa_ctx ffa_ctx;
+
+/* The search of one series (Sec. 5.3 - 5.5).
+ *   tsamp        sampling time tau of the series, seconds, > 0.
+ *   period_min   P_min, seconds; period_max P_max > period_min. The first
+ *                downsampling factor is ds0 = P_min / (bins_min * tsamp) and
+ *                must be >= 1 (FFA_ERR_RANGE otherwise).
+ *   bins_min, bins_max
+ *                number of phase bins per folded profile, 2 <= min <= max.
+ *                Pseudo-octave k downsamples the original series by
+ *                ds0 * f^k, f = (bins_max + 1) / bins_min (Sec. 5.3).
+ *   widths       HOST array of num_widths boxcar widths in bins, strictly
+ *                increasing, 1 <= w < bins_min (Sec. 5.4), at most 32 widths.
+ *   normalise    1: subtract the mean and divide by the population standard
+ *                deviation of the whole series, both computed in FP64 on the
+ *                device (Sec. 5.2); 0: the series is used as given (it should
+ *                then have zero mean and unit variance).
+ *   dtype        ffa_dtype of the series. The downsampled series is stored
+ *                in the same type; folding and S/N accumulate in FP32. */
+typedef struct {
+  double tsamp;
+  double period_min;
+  double period_max;
+  int32_t bins_min;
+  int32_t bins_max;
+  const int32_t* widths;
+  int32_t num_widths;
+  int32_t normalise;
+  int32_t dtype;
+} ffa_search_params;
+
+/* Creates a context on HIP device `device`. *out receives the handle. */
+ffa_status ffa_create(int device, ffa_ctx** out);
+
+/* Waits for the context's work, frees its workspace and the handle. NULL is a no-op. */
+ffa_status ffa_destroy(ffa_ctx* ctx);
+
+/* Static English text of a status code. */
+const char* ffa_status_string(ffa_status s);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next
+ * call on ctx. */
+const char* ffa_last_error(const ffa_ctx* ctx);
+
+/* Number of periodogram rows of a series of nsamp samples (Sec. 2.3, 5.3):
+ * the kept trial periods of every transform of every pseudo-octave. A row of
+ * transform (k, p) with m rows is kept when its period
+ * P_s = tau_k p^2 / (p - s/(m-1)) is below both (p + 1) tau_k, past which
+ * trials overlap the next transform (Sec. 2.3), and P_max. Host only. */
+ffa_status ffa_plan_rows(const ffa_search_params* params, int64_t nsamp, int64_t* rows);
+
+/* Exports the plan row by row, in periodogram order (octave k, bins p, row s;
+ * ascending period). Every HOST array holds `capacity` entries; any may be
+ * NULL. period: P_s in seconds (Eq. for P_s, Sec. 2.3); bins: p; m: rows of
+ * the transform; s: row index; octave: k; ds_fx: downsampling factor of the
+ * octave in 32.32 fixed point. FFA_ERR_BUFFER_TOO_SMALL if capacity < rows. */
+ffa_status ffa_plan_export(const ffa_search_params* params, int64_t nsamp, double* period,
+                           int32_t* bins, int32_t* m, int32_t* s, int32_t* octave,
+                           uint64_t* ds_fx, int64_t capacity);
+
+/* Periodogram of one series (Sec. 5.3 - 5.5).
+ *   series       DEVICE, nsamp samples of params->dtype.
+ *   period_host  HOST, capacity_rows doubles or NULL: trial period of each row.
+ *   bins_host    HOST, capacity_rows int32 or NULL: bins p of each row.
+ *   snr_dev      DEVICE, capacity_rows x num_widths FP32, row-major: for each
+ *                kept trial period and boxcar width, the best S/N over phase.
+ * A degenerate series (zero or non-finite variance with normalise = 1) gives
+ * NaN S/N; ffa_sync_status then reports FFA_ERR_DEGENERATE. */
+ffa_status ffa_search(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                      const ffa_search_params* params, double* period_host, int32_t* bins_host,
+                      float* snr_dev, int64_t capacity_rows, void* stream);
+
+/* Periodograms of nseries series of uneven lengths and parameters.
+ *   series       HOST array of nseries DEVICE pointers.
+ *   nsamp        HOST array of nseries lengths.
+ *   params       HOST array of nseries parameter sets (their num_widths must
+ *                all be equal).
+ *   row_offset   HOST array of nseries: first row of series i in snr_dev; the
+ *                rows of series i are [row_offset[i], row_offset[i] + rows_i).
+ *   snr_dev      DEVICE, capacity_rows x num_widths FP32.
+ *   use_graph    1: capture the device work of the call in a hipGraph the
+ *                first time a batch of this shape is seen and replay it on
+ *                later calls with the same shape and pointers; 0: launch
+ *                directly. */
+ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                            const int64_t* nsamp, const ffa_search_params* params,
+                            const int64_t* row_offset, float* snr_dev, int64_t capacity_rows,
+                            int32_t use_graph, void* stream);
+
+/* Folding transform alone (Sec. 2.1, 2.2), for parity checks: in and out are
+ * DEVICE m x p FP32 arrays, row-major; row s of out is the profile folded along
+ * the path that drifts s bins over the m rows. 1 <= m, 2 <= p <= 1280,
+ * m * p < 2^31. */
+ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, float* out,
+                         void* stream);
+
+/* Normalisation statistics (Sec. 5.2): stats_dev (DEVICE, 2 doubles) receives
+ * the mean and the population standard deviation of the series, computed in
+ * FP64. */
+ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                            double* stats_dev, void* stream);
+
+/* Real-factor downsampling (Sec. 5.3, App. A.4) of one series: output j is
+ * the overlap-weighted sum of the normalised input over the window
+ * [j ds, (j+1) ds), ds = ds_fx / 2^32 samples; with stats_dev = NULL no
+ * normalisation is applied, else (x - mean) / std with stats_dev as written by
+ * ffa_series_stats. out_dev (DEVICE) receives nout samples of `dtype`;
+ * nout <= floor(nsamp * 2^32 / ds_fx), ds_fx >= 2^32. */
+ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                          const double* stats_dev, uint64_t ds_fx, int64_t nout, void* out_dev,
+                          void* stream);
+
+/* Waits for the stream and reports FFA_ERR_DEGENERATE if a series normalised
+ * since the previous call to ffa_sync_status had zero or non-finite variance. */
+ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);
+
+/* Tile shapes used by the search kernels. lds_rows: rows of a profile tile
+ * held in LDS (0 = the largest that fits); levels_per_pass: merge levels per
+ * pass above the bottom subtrees (1..4). */
+typedef struct {
+  int32_t lds_rows;
+  int32_t levels_per_pass;
+} ffa_tiling;
+
+/* Reads or sets the context's tiling. */
+ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out);
+ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* tiling);
+
+/* Times every candidate tiling on a representative batch (same arguments as
+ * ffa_search_batch, outputs to a context-owned buffer), keeps the fastest in
+ * the context and, if cache_path is not NULL, appends it to that text file
+ * keyed by the batch's shape. *best receives the chosen tiling (may be NULL). */
+ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                        const int64_t* nsamp, const ffa_search_params* params,
+                        const char* cache_path, ffa_tiling* best, void* stream);
+
+/* Per-kernel device time of the calls made while timing is on. Each launch
+ * is bracketed by HIP events on the stream it runs on (not inside captured
+ * graphs). */
+typedef struct {
+  double stats_ms;             /* FP64 statistics kernels (Sec. 5.2) */
+  double downsample_ms;        /* downsampling kernel (Sec. 5.3) */
+  double fold_ms;              /* folding-transform + S/N kernels (Sec. 2.2, 5.4) */
+  int64_t stats_launches;
+  int64_t downsample_launches;
+  int64_t fold_launches;
+  int64_t profiles;            /* periodogram rows produced */
+  int64_t folded_cells;        /* sum of m * p over the transforms folded */
+  int64_t input_samples;       /* raw samples read */
+  int64_t downsampled_samples; /* samples written by the downsampler */
+} ffa_kernel_times;
+
+/* Turns per-kernel timing on (1) or off (0) for the calls that follow. */
+ffa_status ffa_set_timing(ffa_ctx* ctx, int32_t enable);
+
+/* Waits for the timed work, returns the totals since the last reset and
+ * resets them when `reset` is 1. */
+ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFA_MI355X_H */

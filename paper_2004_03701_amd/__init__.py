@@ -1,0 +1,308 @@
+"""Python binding of the MI355X FFA periodicity-search library.
+
+Argument marshalling only: every step of the search runs in the HIP kernels
+of ``libffa_mi355x.so`` behind the C ABI declared in ``include/ffa.h``; the
+functions below carry the same names as the C entry points. PyTorch is used
+only for device memory and streams.
+
+The library must have been built (``python -m paper_2004_03701_amd.build``);
+importing the raw entry points without it raises immediately, there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffa_mi355x.so")
+
+FFA_OK = 0
+FFA_ERR_INVALID_ARG = -1
+FFA_ERR_RANGE = -2
+FFA_ERR_BUFFER_TOO_SMALL = -3
+FFA_ERR_NOMEM = -4
+FFA_ERR_DEVICE = -5
+FFA_ERR_DEGENERATE = -6
+FFA_ERR_NOT_IMPLEMENTED = -7
+
+FFA_F32, FFA_BF16, FFA_F16 = 0, 1, 2
+
+EXPORTED = (
+    "ffa_create", "ffa_destroy", "ffa_status_string", "ffa_last_error", "ffa_plan_rows",
+    "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
+    "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
+    "ffa_set_timing", "ffa_read_timing",
+)
+
+
+class ffa_search_params(ctypes.Structure):
+    _fields_ = [
+        ("tsamp", ctypes.c_double),
+        ("period_min", ctypes.c_double),
+        ("period_max", ctypes.c_double),
+        ("bins_min", ctypes.c_int32),
+        ("bins_max", ctypes.c_int32),
+        ("widths", ctypes.POINTER(ctypes.c_int32)),
+        ("num_widths", ctypes.c_int32),
+        ("normalise", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+    ]
+
+
+class ffa_tiling(ctypes.Structure):
+    _fields_ = [("lds_rows", ctypes.c_int32), ("levels_per_pass", ctypes.c_int32)]
+
+
+class ffa_kernel_times(ctypes.Structure):
+    _fields_ = [
+        ("stats_ms", ctypes.c_double),
+        ("downsample_ms", ctypes.c_double),
+        ("fold_ms", ctypes.c_double),
+        ("stats_launches", ctypes.c_int64),
+        ("downsample_launches", ctypes.c_int64),
+        ("fold_launches", ctypes.c_int64),
+        ("profiles", ctypes.c_int64),
+        ("folded_cells", ctypes.c_int64),
+        ("input_samples", ctypes.c_int64),
+        ("downsampled_samples", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FFAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2004_03701_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    P = ctypes.POINTER
+    pp = P(ffa_search_params)
+    sig = {
+        "ffa_create": ([ctypes.c_int, P(vp)], i32),
+        "ffa_destroy": ([vp], i32),
+        "ffa_status_string": ([i32], ctypes.c_char_p),
+        "ffa_last_error": ([vp], ctypes.c_char_p),
+        "ffa_plan_rows": ([pp, i64, P(i64)], i32),
+        "ffa_plan_export": ([pp, i64, vp, vp, vp, vp, vp, vp, i64], i32),
+        "ffa_search": ([vp, vp, i64, pp, vp, vp, vp, i64, vp], i32),
+        "ffa_search_batch": ([vp, i32, P(vp), P(i64), pp, P(i64), vp, i64, i32, vp], i32),
+        "ffa_transform": ([vp, vp, i32, i32, vp, vp], i32),
+        "ffa_series_stats": ([vp, vp, i64, i32, vp, vp], i32),
+        "ffa_downsample": ([vp, vp, i64, i32, vp, u64, i64, vp, vp], i32),
+        "ffa_sync_status": ([vp, vp], i32),
+        "ffa_get_tiling": ([vp, P(ffa_tiling)], i32),
+        "ffa_set_tiling": ([vp, P(ffa_tiling)], i32),
+        "ffa_autotune": ([vp, i32, P(vp), P(i64), pp, ctypes.c_char_p, P(ffa_tiling), vp], i32),
+        "ffa_set_timing": ([vp, i32], i32),
+        "ffa_read_timing": ([vp, P(ffa_kernel_times), i32], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return lib().ffa_status_string(st).decode()
+
+
+def _check(st: int, ctx=None):
+    if st != FFA_OK:
+        msg = ""
+        if ctx is not None:
+            msg = lib().ffa_last_error(ctx).decode()
+        raise FFAError(st, msg or status_string(st))
+
+
+def make_params(tsamp: float, period_min: float, period_max: float, bins_min: int,
+                bins_max: int, widths: Sequence[int], normalise: bool = True,
+                dtype: int = FFA_F32) -> ffa_search_params:
+    """Parameter struct; keeps its widths array alive as an attribute."""
+    w = (ctypes.c_int32 * len(widths))(*[int(v) for v in widths])
+    prm = ffa_search_params(float(tsamp), float(period_min), float(period_max), int(bins_min),
+                            int(bins_max), ctypes.cast(w, ctypes.POINTER(ctypes.c_int32)),
+                            len(widths), 1 if normalise else 0, int(dtype))
+    prm._widths_keepalive = w
+    return prm
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+# ---------------------------------------------------------------------------
+# Entry points, same names as the C ABI
+# ---------------------------------------------------------------------------
+
+def ffa_create(device: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib().ffa_create(device, ctypes.byref(h)))
+    return h
+
+
+def ffa_destroy(ctx) -> None:
+    _check(lib().ffa_destroy(ctx))
+
+
+def ffa_last_error(ctx) -> str:
+    return lib().ffa_last_error(ctx).decode()
+
+
+def ffa_plan_rows(params: ffa_search_params, nsamp: int) -> int:
+    rows = ctypes.c_int64()
+    _check(lib().ffa_plan_rows(ctypes.byref(params), nsamp, ctypes.byref(rows)))
+    return rows.value
+
+
+def ffa_plan_export(params: ffa_search_params, nsamp: int) -> dict:
+    n = ffa_plan_rows(params, nsamp)
+    out = dict(period=np.empty(n, np.float64), bins=np.empty(n, np.int32),
+               m=np.empty(n, np.int32), s=np.empty(n, np.int32),
+               octave=np.empty(n, np.int32), ds_fx=np.empty(n, np.uint64))
+    a = [out[k].ctypes.data for k in ("period", "bins", "m", "s", "octave", "ds_fx")]
+    _check(lib().ffa_plan_export(ctypes.byref(params), nsamp, *a, n))
+    return out
+
+
+def ffa_search(ctx, series, params: ffa_search_params, snr=None, stream=None,
+               want_labels: bool = True):
+    """Periodogram of one device series (torch tensor). Returns
+    (periods, bins, snr) with periods/bins as numpy arrays (None unless
+    want_labels) and snr a device tensor rows x num_widths."""
+    import torch
+    nsamp = series.numel()
+    rows = ffa_plan_rows(params, nsamp)
+    if snr is None:
+        snr = torch.empty((rows, params.num_widths), dtype=torch.float32, device=series.device)
+    per = np.empty(rows, np.float64) if want_labels else None
+    bins = np.empty(rows, np.int32) if want_labels else None
+    st = lib().ffa_search(ctx, series.data_ptr(), nsamp, ctypes.byref(params),
+                          per.ctypes.data if want_labels else None,
+                          bins.ctypes.data if want_labels else None,
+                          snr.data_ptr(), snr.shape[0], _stream(stream))
+    _check(st, ctx)
+    return per, bins, snr
+
+
+def ffa_search_batch(ctx, series: Sequence, params: Sequence[ffa_search_params], snr=None,
+                     row_offset: Optional[Sequence[int]] = None, use_graph: bool = False,
+                     stream=None):
+    """Periodograms of several device series (torch tensors, uneven lengths).
+    Returns (snr, row_offset)."""
+    import torch
+    n = len(series)
+    nsamp = [int(s.numel()) for s in series]
+    if row_offset is None:
+        rows = [ffa_plan_rows(p, ns) for p, ns in zip(params, nsamp)]
+        row_offset = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
+        total = int(sum(rows))
+    else:
+        total = None
+    if snr is None:
+        if total is None:
+            rows = [ffa_plan_rows(p, ns) for p, ns in zip(params, nsamp)]
+            total = int(max(o + r for o, r in zip(row_offset, rows)))
+        snr = torch.empty((total, params[0].num_widths), dtype=torch.float32,
+                          device=series[0].device)
+    ptrs = (ctypes.c_void_p * n)(*[s.data_ptr() for s in series])
+    ns = (ctypes.c_int64 * n)(*nsamp)
+    prm = (ffa_search_params * n)(*params)
+    ro = (ctypes.c_int64 * n)(*[int(v) for v in row_offset])
+    st = lib().ffa_search_batch(ctx, n, ptrs, ns, prm, ro, snr.data_ptr(), snr.shape[0],
+                                1 if use_graph else 0, _stream(stream))
+    _check(st, ctx)
+    return snr, np.asarray(row_offset, dtype=np.int64)
+
+
+def ffa_transform(ctx, x, out=None, stream=None):
+    """Folding transform of a device m x p float32 tensor."""
+    import torch
+    m, p = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().ffa_transform(ctx, x.data_ptr(), m, p, out.data_ptr(), _stream(stream)), ctx)
+    return out
+
+
+def ffa_series_stats(ctx, series, dtype: int = FFA_F32, stream=None):
+    import torch
+    st = torch.empty(2, dtype=torch.float64, device=series.device)
+    _check(lib().ffa_series_stats(ctx, series.data_ptr(), series.numel(), dtype, st.data_ptr(),
+                                  _stream(stream)), ctx)
+    return st
+
+
+def ffa_downsample(ctx, series, ds_fx: int, nout: int, stats=None, dtype: int = FFA_F32,
+                   stream=None):
+    import torch
+    tdt = {FFA_F32: torch.float32, FFA_BF16: torch.bfloat16, FFA_F16: torch.float16}[dtype]
+    out = torch.empty(nout, dtype=tdt, device=series.device)
+    _check(lib().ffa_downsample(ctx, series.data_ptr(), series.numel(), dtype,
+                                _ptr(stats), ds_fx, nout, out.data_ptr(), _stream(stream)), ctx)
+    return out
+
+
+def ffa_sync_status(ctx, stream=None) -> int:
+    return lib().ffa_sync_status(ctx, _stream(stream))
+
+
+def ffa_get_tiling(ctx) -> ffa_tiling:
+    t = ffa_tiling()
+    _check(lib().ffa_get_tiling(ctx, ctypes.byref(t)), ctx)
+    return t
+
+
+def ffa_set_tiling(ctx, lds_rows: int = 0, levels_per_pass: int = 4) -> None:
+    t = ffa_tiling(lds_rows, levels_per_pass)
+    _check(lib().ffa_set_tiling(ctx, ctypes.byref(t)), ctx)
+
+
+def ffa_autotune(ctx, series: Sequence, params: Sequence[ffa_search_params],
+                 cache_path: Optional[str] = None, stream=None) -> ffa_tiling:
+    n = len(series)
+    ptrs = (ctypes.c_void_p * n)(*[s.data_ptr() for s in series])
+    ns = (ctypes.c_int64 * n)(*[int(s.numel()) for s in series])
+    prm = (ffa_search_params * n)(*params)
+    best = ffa_tiling()
+    _check(lib().ffa_autotune(ctx, n, ptrs, ns, prm,
+                              cache_path.encode() if cache_path else None, ctypes.byref(best),
+                              _stream(stream)), ctx)
+    return best
+
+
+def ffa_set_timing(ctx, enable: bool) -> None:
+    _check(lib().ffa_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def ffa_read_timing(ctx, reset: bool = True) -> dict:
+    t = ffa_kernel_times()
+    _check(lib().ffa_read_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
+    return t.as_dict()

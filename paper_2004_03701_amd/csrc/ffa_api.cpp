@@ -1,0 +1,772 @@
+// C ABI of the FFA search: argument checks, plan and table caches, device
+// workspace, launches and graph capture.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ffa.h"
+#include "ffa_internal.hpp"
+#include "ffa_kernels.hpp"
+#include "ffa_plan.hpp"
+
+namespace ffa {
+hipError_t launch_norm_from_stats(const double* stats, float* norm, hipStream_t stream);
+}
+
+using namespace ffa;
+
+namespace {
+
+// Grow-only device buffer (pointers stay valid for captured graphs).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (ptr) (void)hipFree(ptr);
+  }
+  hipError_t reserve(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (ptr) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      (void)hipFree(ptr);
+      ptr = nullptr;
+      bytes = 0;
+    }
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+size_t dtype_bytes(int dt) { return dt == FFA_F32 ? 4 : 2; }
+
+// Key of a plan: every parameter that changes it.
+std::string plan_key(const ffa_search_params& a, int64_t nsamp) {
+  std::ostringstream k;
+  k.precision(17);
+  k << a.tsamp << ',' << a.period_min << ',' << a.period_max << ',' << a.bins_min << ','
+    << a.bins_max << ',' << nsamp << ',' << a.num_widths << ':';
+  for (int q = 0; q < a.num_widths; ++q) k << a.widths[q] << ',';
+  return k.str();
+}
+
+// Device tables of one batch job: series, octaves, transforms, scales and
+// tiles, plus the launch list.
+struct Launch {
+  size_t tile_off;
+  int32_t ntiles;
+};
+struct Group {
+  std::vector<Launch> passes;
+};
+struct Job {
+  int32_t nseries = 0;
+  int32_t dtype = 0;
+  int32_t num_widths = 0;
+  int32_t wmax = 0;
+  int32_t max_p = 0;
+  int32_t widths[kMaxWidths] = {0};
+  bool any_normalise = false;
+  int32_t max_halo = 0;
+  int32_t block_samples = 0;
+  int64_t ds_blocks = 0;
+  int64_t ds_total = 0;     // elements of the downsampled buffer
+  int64_t scr_cells = 0;    // floats per scratch buffer
+  int64_t rows = 0;         // periodogram rows
+  int64_t cells = 0;        // sum of m * p
+  int64_t input_samples = 0;
+  std::vector<Group> groups;
+  DevBuf series, oct, xf, scales, tiles;
+  int32_t stats_blocks = 0;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+}  // namespace
+
+// Event pairs bracketing timed launches.
+struct TimedLaunch {
+  int kind;  // 0 stats, 1 downsample, 2 fold
+  hipEvent_t start, stop;
+};
+
+struct ffa_ctx {
+  int device = 0;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
+  ffa_kernel_times times{};
+  std::string last_error;
+  Tiling tiling;
+  std::map<std::string, std::shared_ptr<SeriesPlan>> plans;
+  std::map<std::string, std::shared_ptr<Job>> jobs;
+  std::map<std::string, std::shared_ptr<GraphEntry>> graphs;
+  DevBuf ds_buf, scr0, scr1, stats, norm, partials, flag, tune_out;
+  size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
+};
+
+namespace {
+
+ffa_status fail(ffa_ctx* ctx, ffa_status st, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+ffa_status hip_fail(ffa_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? FFA_ERR_NOMEM : FFA_ERR_DEVICE, m);
+}
+
+#define HIP_TRY(ctx, call, what)                    \
+  do {                                              \
+    hipError_t _e = (call);                         \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+ffa_status get_plan(ffa_ctx* ctx, const ffa_search_params& a, int64_t nsamp,
+                    std::shared_ptr<SeriesPlan>* out) {
+  std::string err;
+  ffa_status st = validate_params(a, &err);
+  if (st != FFA_OK) return fail(ctx, st, err);
+  const std::string key = plan_key(a, nsamp);
+  if (ctx) {
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+      *out = it->second;
+      return FFA_OK;
+    }
+  }
+  auto plan = std::make_shared<SeriesPlan>();
+  st = build_series_plan(a, nsamp, plan.get(), &err);
+  if (st != FFA_OK) return fail(ctx, st, err);
+  if (ctx) ctx->plans[key] = plan;
+  *out = plan;
+  return FFA_OK;
+}
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+  hipError_t e = b.reserve(std::max<size_t>(v.size() * sizeof(T), 16));
+  if (e != hipSuccess) return e;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Builds the device tables of a batch of series. Series pointers are stored
+// in the tables, so the job is keyed by them too.
+ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                     const int64_t* nsamp, const ffa_search_params* params,
+                     const int64_t* row_offset, const std::vector<std::shared_ptr<SeriesPlan>>& plans,
+                     Job* job) {
+  job->nseries = nseries;
+  job->dtype = params[0].dtype;
+  job->num_widths = params[0].num_widths;
+  for (int q = 0; q < job->num_widths; ++q) job->widths[q] = params[0].widths[q];
+  job->wmax = job->widths[job->num_widths - 1];
+  std::vector<SeriesDev> sd(nseries);
+  std::vector<OctaveDev> od;
+  std::vector<XformDesc> xf;
+  std::vector<float> scales;
+  int64_t ds_off = 0, chunk = 0;
+  int32_t max_halo = 0;
+  for (int i = 0; i < nseries; ++i)
+    max_halo = std::max<int32_t>(max_halo, (int32_t)(plans[i]->ds_fx_max >> 32) + 2);
+  job->max_halo = max_halo;
+  job->block_samples = downsample_block_samples(max_halo);
+  // transforms grouped so that each group's scratch fits the budget
+  struct GroupSpan {
+    size_t xf0, xf1;
+    int64_t cells;
+  };
+  std::vector<GroupSpan> spans;
+  int64_t gcells = 0;
+  size_t gx0 = 0;
+  for (int i = 0; i < nseries; ++i) {
+    const SeriesPlan& pl = *plans[i];
+    const ffa_search_params& a = params[i];
+    sd[i].ptr = series[i];
+    sd[i].nsamp = nsamp[i];
+    sd[i].chunk0 = chunk;
+    sd[i].oct0 = (int32_t)od.size();
+    sd[i].noct = (int32_t)pl.oct.size();
+    sd[i].normalise = a.normalise;
+    sd[i].halo = max_halo;
+    if (a.normalise) job->any_normalise = true;
+    chunk += (nsamp[i] + job->block_samples - 1) / job->block_samples;
+    for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
+    if ((size_t)(gcells + pl.cells) > ctx->scratch_budget_cells && gcells > 0) {
+      spans.push_back(GroupSpan{gx0, xf.size(), gcells});
+      gx0 = xf.size();
+      gcells = 0;
+    }
+    for (const Transform& t : pl.tr) {
+      XformDesc x;
+      x.in_off = ds_off + pl.oct[t.octave].ds_off;
+      x.scr_off = gcells;
+      x.out_row0 = row_offset[i] + t.row0;
+      x.m = t.m;
+      x.p = t.p;
+      x.keep = t.keep;
+      x.scale_off = (int32_t)scales.size();
+      const double var = pl.oct[t.octave].var;
+      for (int q = 0; q < a.num_widths; ++q)
+        scales.push_back((float)(1.0 / sqrt((double)t.m * (double)a.widths[q] * var)));
+      gcells += (int64_t)t.m * t.p;
+      job->max_p = std::max(job->max_p, t.p);
+      xf.push_back(x);
+    }
+    ds_off += pl.ds_total;
+    job->rows += pl.rows;
+    job->cells += pl.cells;
+    job->input_samples += nsamp[i];
+  }
+  spans.push_back(GroupSpan{gx0, xf.size(), gcells});
+  job->ds_total = ds_off;
+  job->ds_blocks = chunk;
+  std::vector<TileDesc> tiles;
+  job->scr_cells = 0;
+  for (const GroupSpan& g : spans) {
+    std::vector<std::vector<TileDesc>> passes;
+    for (size_t k = g.xf0; k < g.xf1; ++k) {
+      const XformDesc& x = xf[k];
+      plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
+                           rows_capacity(x.p, ctx->tiling.lds_rows),
+                           ctx->tiling.levels_per_pass, false, &passes);
+    }
+    Group grp;
+    for (auto& ps : passes) {
+      grp.passes.push_back(Launch{tiles.size(), (int32_t)ps.size()});
+      tiles.insert(tiles.end(), ps.begin(), ps.end());
+    }
+    job->groups.push_back(grp);
+    job->scr_cells = std::max(job->scr_cells, g.cells);
+  }
+  // stats: enough blocks per series to fill the chip
+  int64_t maxn = 0;
+  for (int i = 0; i < nseries; ++i) maxn = std::max(maxn, nsamp[i]);
+  job->stats_blocks = (int32_t)std::min<int64_t>(
+      std::max<int64_t>(1, (2048 + nseries - 1) / nseries), std::max<int64_t>(1, maxn / 4096));
+  HIP_TRY(ctx, upload(job->series, sd), "upload series table");
+  HIP_TRY(ctx, upload(job->oct, od), "upload octave table");
+  HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
+  HIP_TRY(ctx, upload(job->scales, scales), "upload scale table");
+  HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
+  return FFA_OK;
+}
+
+// Grows the context workspace for a job. Captured graphs hold the old
+// addresses, so they are dropped whenever a buffer moves.
+ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
+  const size_t db = dtype_bytes(job.dtype);
+  DevBuf* bufs[] = {&ctx->ds_buf, &ctx->scr0, &ctx->scr1, &ctx->stats,
+                    &ctx->norm,   &ctx->partials, &ctx->flag};
+  const size_t want[] = {(size_t)job.ds_total * db + 16,
+                         (size_t)job.scr_cells * 4 + 16,
+                         (size_t)job.scr_cells * 4 + 16,
+                         (size_t)job.nseries * 2 * sizeof(double),
+                         (size_t)job.nseries * 2 * sizeof(float),
+                         (size_t)job.nseries * job.stats_blocks * 2 * sizeof(double),
+                         16};
+  for (int b = 0; b < 7; ++b) {
+    void* before = bufs[b]->ptr;
+    HIP_TRY(ctx, bufs[b]->reserve(want[b]), "allocate workspace");
+    if (before && bufs[b]->ptr != before) ctx->graphs.clear();
+  }
+  return FFA_OK;
+}
+
+hipError_t take_event(ffa_ctx* ctx, hipEvent_t* ev) {
+  if (!ctx->event_pool.empty()) {
+    *ev = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(ev);
+}
+
+// Brackets a launch with events when timing is on.
+struct TimedScope {
+  ffa_ctx* ctx;
+  int kind;
+  hipStream_t stream;
+  bool on;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedScope(ffa_ctx* c, int k, hipStream_t s, bool enabled) : ctx(c), kind(k), stream(s), on(enabled) {
+    if (on && take_event(ctx, &a) == hipSuccess && take_event(ctx, &b) == hipSuccess)
+      on = hipEventRecord(a, stream) == hipSuccess;
+    else
+      on = false;
+  }
+  ~TimedScope() {
+    if (on && hipEventRecord(b, stream) == hipSuccess) ctx->pending.push_back(TimedLaunch{kind, a, b});
+  }
+};
+
+// Queues the device work of a job.
+ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, bool timed) {
+  ffa_status rst = reserve_job(ctx, job);
+  if (rst != FFA_OK) return rst;
+  if (timed) {
+    ctx->times.profiles += job.rows;
+    ctx->times.folded_cells += job.cells;
+    ctx->times.input_samples += job.input_samples;
+    ctx->times.downsampled_samples += job.ds_total;
+  }
+  const SeriesDev* sd = job.series.as<SeriesDev>();
+  if (job.any_normalise) {
+    TimedScope ts(ctx, 0, stream, timed);
+    HIP_TRY(ctx, launch_stats(sd, job.nseries, job.dtype, job.stats_blocks,
+                              ctx->partials.as<double>(), ctx->stats.as<double>(),
+                              ctx->norm.as<float>(), ctx->flag.as<int32_t>(), stream),
+            "stats kernels");
+  }
+  {
+  TimedScope ts(ctx, 1, stream, timed);
+  HIP_TRY(ctx, launch_downsample(sd, job.nseries, job.oct.as<OctaveDev>(), ctx->norm.as<float>(),
+                                 job.dtype, ctx->ds_buf.ptr, job.dtype, job.ds_blocks,
+                                 job.block_samples, job.max_halo, stream),
+          "downsample kernel");
+  }
+  PassArgs pa{};
+  pa.lds_rows_cap = ctx->tiling.lds_rows;
+  pa.xf = job.xf.as<XformDesc>();
+  pa.in = ctx->ds_buf.ptr;
+  pa.in_dtype = job.dtype;
+  pa.num_widths = job.num_widths;
+  pa.scr0 = ctx->scr0.as<float>();
+  pa.scr1 = ctx->scr1.as<float>();
+  pa.out_rows = nullptr;
+  pa.snr = snr;
+  pa.scales = job.scales.as<float>();
+  for (int q = 0; q < kMaxWidths; ++q) pa.widths[q] = job.widths[q];
+  pa.wmax = job.wmax;
+  pa.max_p = job.max_p;
+  const TileDesc* tiles = job.tiles.as<TileDesc>();
+  for (const Group& g : job.groups) {
+    for (const Launch& l : g.passes) {
+      pa.tiles = tiles + l.tile_off;
+      pa.ntiles = l.ntiles;
+      TimedScope ts(ctx, 2, stream, timed);
+      HIP_TRY(ctx, launch_pass(pa, stream), "fold pass kernel");
+    }
+  }
+  return FFA_OK;
+}
+
+std::string job_key(int32_t nseries, const void* const* series, const int64_t* nsamp,
+                    const ffa_search_params* params, const int64_t* row_offset,
+                    const Tiling& tiling) {
+  std::ostringstream k;
+  k << nseries << '|' << tiling.lds_rows << ',' << tiling.levels_per_pass << '|';
+  for (int i = 0; i < nseries; ++i)
+    k << series[i] << ',' << row_offset[i] << ',' << params[i].normalise << ','
+      << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
+  return k.str();
+}
+
+ffa_status check_batch_args(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                            const int64_t* nsamp, const ffa_search_params* params) {
+  if (!series || !nsamp || !params || nseries < 1)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "null batch array or nseries < 1");
+  for (int i = 0; i < nseries; ++i) {
+    if (!series[i]) return fail(ctx, FFA_ERR_INVALID_ARG, "null series pointer");
+    if (params[i].num_widths != params[0].num_widths || params[i].dtype != params[0].dtype)
+      return fail(ctx, FFA_ERR_INVALID_ARG, "all series of a batch need the same dtype and number of widths");
+    if (params[i].widths && params[0].widths)
+      for (int q = 0; q < params[0].num_widths && q < params[i].num_widths; ++q)
+        if (params[i].widths[q] != params[0].widths[q])
+          return fail(ctx, FFA_ERR_INVALID_ARG, "all series of a batch need the same widths");
+  }
+  return FFA_OK;
+}
+
+// Shared body of ffa_search and ffa_search_batch.
+ffa_status run_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                     const int64_t* nsamp, const ffa_search_params* params,
+                     const int64_t* row_offset, float* snr, int64_t capacity_rows,
+                     int32_t use_graph, hipStream_t stream) {
+  ffa_status st = check_batch_args(ctx, nseries, series, nsamp, params);
+  if (st != FFA_OK) return st;
+  if (!row_offset || !snr) return fail(ctx, FFA_ERR_INVALID_ARG, "null row_offset or snr");
+  std::vector<std::shared_ptr<SeriesPlan>> plans(nseries);
+  for (int i = 0; i < nseries; ++i) {
+    st = get_plan(ctx, params[i], nsamp[i], &plans[i]);
+    if (st != FFA_OK) return st;
+    if (row_offset[i] < 0 || row_offset[i] + plans[i]->rows > capacity_rows)
+      return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
+  }
+  const std::string key = job_key(nseries, series, nsamp, params, row_offset, ctx->tiling);
+  std::shared_ptr<Job> job;
+  auto it = ctx->jobs.find(key);
+  if (it != ctx->jobs.end()) {
+    job = it->second;
+  } else {
+    if (ctx->jobs.size() > 64) ctx->jobs.clear();
+    job = std::make_shared<Job>();
+    st = build_job(ctx, nseries, series, nsamp, params, row_offset, plans, job.get());
+    if (st != FFA_OK) return st;
+    ctx->jobs[key] = job;
+  }
+  if (!use_graph) return enqueue_job(ctx, *job, snr, stream, ctx->timing);
+  std::ostringstream gk;
+  gk << key << "|snr=" << (const void*)snr << "|stream=" << (const void*)stream;
+  st = reserve_job(ctx, *job);
+  if (st != FFA_OK) return st;
+  auto git = ctx->graphs.find(gk.str());
+  if (git == ctx->graphs.end()) {
+    // allocate everything before capture so no allocation happens inside it
+    st = reserve_job(ctx, *job);
+    if (st != FFA_OK) return st;
+    hipStream_t cap = stream;
+    bool own = false;
+    if (cap == nullptr) {
+      HIP_TRY(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream");
+      own = true;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    ffa_status est = enqueue_job(ctx, *job, snr, cap, false);
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (own) (void)hipStreamDestroy(cap);
+    if (est != FFA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return est;
+    }
+    if (ce != hipSuccess) return hip_fail(ctx, ce, "end capture");
+    auto ge = std::make_shared<GraphEntry>();
+    hipError_t ie = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ctx, ie, "instantiate graph");
+    if (ctx->graphs.size() > 16) ctx->graphs.clear();
+    git = ctx->graphs.emplace(gk.str(), ge).first;
+  }
+  HIP_TRY(ctx, hipGraphLaunch(git->second->exec, stream), "graph launch");
+  return FFA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ffa_status ffa_create(int device, ffa_ctx** out) {
+  if (!out) return FFA_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FFA_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FFA_ERR_DEVICE;
+  ffa_ctx* c = new (std::nothrow) ffa_ctx();
+  if (!c) return FFA_ERR_NOMEM;
+  c->device = device;
+  *out = c;
+  return FFA_OK;
+}
+
+ffa_status ffa_destroy(ffa_ctx* ctx) {
+  if (!ctx) return FFA_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (const TimedLaunch& t : ctx->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return FFA_OK;
+}
+
+const char* ffa_status_string(ffa_status s) {
+  switch (s) {
+    case FFA_OK: return "ok";
+    case FFA_ERR_INVALID_ARG: return "invalid argument";
+    case FFA_ERR_RANGE: return "period range not searchable with these parameters";
+    case FFA_ERR_BUFFER_TOO_SMALL: return "output buffer too small";
+    case FFA_ERR_NOMEM: return "out of memory";
+    case FFA_ERR_DEVICE: return "HIP device error";
+    case FFA_ERR_DEGENERATE: return "degenerate series (zero or non-finite variance)";
+    case FFA_ERR_NOT_IMPLEMENTED: return "not implemented";
+  }
+  return "unknown status";
+}
+
+const char* ffa_last_error(const ffa_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+ffa_status ffa_plan_rows(const ffa_search_params* params, int64_t nsamp, int64_t* rows) {
+  if (!params || !rows) return FFA_ERR_INVALID_ARG;
+  std::shared_ptr<SeriesPlan> plan;
+  ffa_status st = get_plan(nullptr, *params, nsamp, &plan);
+  if (st != FFA_OK) return st;
+  *rows = plan->rows;
+  return FFA_OK;
+}
+
+ffa_status ffa_plan_export(const ffa_search_params* params, int64_t nsamp, double* period,
+                           int32_t* bins, int32_t* m, int32_t* s, int32_t* octave,
+                           uint64_t* ds_fx, int64_t capacity) {
+  if (!params) return FFA_ERR_INVALID_ARG;
+  std::shared_ptr<SeriesPlan> plan;
+  ffa_status st = get_plan(nullptr, *params, nsamp, &plan);
+  if (st != FFA_OK) return st;
+  if (capacity < plan->rows) return FFA_ERR_BUFFER_TOO_SMALL;
+  for (const Transform& t : plan->tr) {
+    const Octave& o = plan->oct[t.octave];
+    for (int32_t r = 0; r < t.keep; ++r) {
+      const int64_t row = t.row0 + r;
+      if (period) period[row] = trial_period(r, t.m, t.p, o.tau);
+      if (bins) bins[row] = t.p;
+      if (m) m[row] = t.m;
+      if (s) s[row] = r;
+      if (octave) octave[row] = t.octave;
+      if (ds_fx) ds_fx[row] = o.ds_fx;
+    }
+  }
+  return FFA_OK;
+}
+
+ffa_status ffa_search(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                      const ffa_search_params* params, double* period_host, int32_t* bins_host,
+                      float* snr_dev, int64_t capacity_rows, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !params || !snr_dev)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "null series, params or snr pointer");
+  std::shared_ptr<SeriesPlan> plan;
+  ffa_status st = get_plan(ctx, *params, nsamp, &plan);
+  if (st != FFA_OK) return st;
+  if (capacity_rows < plan->rows)
+    return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
+  if (period_host || bins_host) {
+    for (const Transform& t : plan->tr) {
+      const Octave& o = plan->oct[t.octave];
+      for (int32_t r = 0; r < t.keep; ++r) {
+        if (period_host) period_host[t.row0 + r] = trial_period(r, t.m, t.p, o.tau);
+        if (bins_host) bins_host[t.row0 + r] = t.p;
+      }
+    }
+  }
+  const int64_t zero = 0;
+  return run_batch(ctx, 1, &series, &nsamp, params, &zero, snr_dev, capacity_rows, 0,
+                   static_cast<hipStream_t>(stream));
+}
+
+ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                            const int64_t* nsamp, const ffa_search_params* params,
+                            const int64_t* row_offset, float* snr_dev, int64_t capacity_rows,
+                            int32_t use_graph, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  return run_batch(ctx, nseries, series, nsamp, params, row_offset, snr_dev, capacity_rows,
+                   use_graph, static_cast<hipStream_t>(stream));
+}
+
+ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, float* out,
+                         void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!in || !out) return fail(ctx, FFA_ERR_INVALID_ARG, "null in or out");
+  if (m < 1 || p < 2 || p > kMaxBins || (int64_t)m * p > (int64_t(1) << 31))
+    return fail(ctx, FFA_ERR_INVALID_ARG, "need 1 <= m, 2 <= p <= 1280, m * p < 2^31");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<XformDesc> xf(1);
+  xf[0].in_off = 0;
+  xf[0].scr_off = 0;
+  xf[0].out_row0 = 0;
+  xf[0].m = m;
+  xf[0].p = p;
+  xf[0].keep = m;
+  xf[0].scale_off = 0;
+  std::vector<std::vector<TileDesc>> passes;
+  if (m == 1) {
+    HIP_TRY(ctx, hipMemcpyAsync(out, in, (size_t)p * 4, hipMemcpyDeviceToDevice, st), "copy");
+    return FFA_OK;
+  }
+  plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling.lds_rows),
+                       ctx->tiling.levels_per_pass, true, &passes);
+  std::vector<TileDesc> tiles;
+  std::vector<Launch> launches;
+  for (auto& ps : passes) {
+    launches.push_back(Launch{tiles.size(), (int32_t)ps.size()});
+    tiles.insert(tiles.end(), ps.begin(), ps.end());
+  }
+  // per-call tables live as long as the context (kept in a small job)
+  auto job = std::make_shared<Job>();
+  HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
+  HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
+  HIP_TRY(ctx, ctx->scr0.reserve((size_t)m * p * 4 + 16), "allocate scratch");
+  HIP_TRY(ctx, ctx->scr1.reserve((size_t)m * p * 4 + 16), "allocate scratch");
+  PassArgs pa{};
+  pa.lds_rows_cap = ctx->tiling.lds_rows;
+  pa.xf = job->xf.as<XformDesc>();
+  pa.in = in;
+  pa.in_dtype = FFA_F32;
+  pa.num_widths = 1;
+  pa.widths[0] = 1;
+  pa.wmax = 1;
+  pa.max_p = p;
+  pa.scr0 = ctx->scr0.as<float>();
+  pa.scr1 = ctx->scr1.as<float>();
+  pa.out_rows = out;
+  for (const Launch& l : launches) {
+    pa.tiles = job->tiles.as<TileDesc>() + l.tile_off;
+    pa.ntiles = l.ntiles;
+    HIP_TRY(ctx, launch_pass(pa, st), "fold pass kernel");
+  }
+  // keep the tables alive until the work is done
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  return FFA_OK;
+}
+
+ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                            double* stats_dev, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !stats_dev) return fail(ctx, FFA_ERR_INVALID_ARG, "null series or stats");
+  if (nsamp < 1 || nsamp > INT32_MAX) return fail(ctx, FFA_ERR_INVALID_ARG, "nsamp out of range");
+  if (dtype != FFA_F32 && dtype != FFA_BF16 && dtype != FFA_F16)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "unknown dtype");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SeriesDev sd{series, nsamp, 0, 0, 0, 1, 0};
+  DevBuf tmp;
+  HIP_TRY(ctx, tmp.reserve(sizeof(SeriesDev)), "allocate");
+  HIP_TRY(ctx, hipMemcpy(tmp.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
+  const int32_t bps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2048, nsamp / 4096));
+  HIP_TRY(ctx, ctx->partials.reserve((size_t)bps * 2 * sizeof(double)), "allocate");
+  HIP_TRY(ctx, ctx->norm.reserve(2 * sizeof(float)), "allocate");
+  HIP_TRY(ctx, ctx->flag.reserve(16), "allocate");
+  HIP_TRY(ctx, launch_stats(tmp.as<SeriesDev>(), 1, dtype, bps, ctx->partials.as<double>(),
+                            stats_dev, ctx->norm.as<float>(), ctx->flag.as<int32_t>(), st),
+          "stats kernels");
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  return FFA_OK;
+}
+
+ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                          const double* stats_dev, uint64_t ds_fx, int64_t nout, void* out_dev,
+                          void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !out_dev) return fail(ctx, FFA_ERR_INVALID_ARG, "null series or out");
+  if (nsamp < 1 || nsamp > INT32_MAX) return fail(ctx, FFA_ERR_INVALID_ARG, "nsamp out of range");
+  if (dtype != FFA_F32 && dtype != FFA_BF16 && dtype != FFA_F16)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "unknown dtype");
+  if (ds_fx < (uint64_t(1) << 32) || (ds_fx >> 32) > (uint64_t)nsamp)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "need 2^32 <= ds_fx <= nsamp * 2^32");
+  const int64_t nmax = (int64_t)(((uint64_t)nsamp << 32) / ds_fx);
+  if (nout < 0 || nout > nmax) return fail(ctx, FFA_ERR_INVALID_ARG, "nout too large");
+  if (nout == 0) return FFA_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t halo = (int32_t)(ds_fx >> 32) + 2;
+  const int32_t bs = downsample_block_samples(halo);
+  SeriesDev sd{series, nsamp, 0, 0, 1, stats_dev ? 1 : 0, halo};
+  OctaveDev od{ds_fx, nout, 0};
+  DevBuf t1, t2;
+  HIP_TRY(ctx, t1.reserve(sizeof sd), "allocate");
+  HIP_TRY(ctx, t2.reserve(sizeof od), "allocate");
+  HIP_TRY(ctx, hipMemcpy(t1.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
+  HIP_TRY(ctx, hipMemcpy(t2.ptr, &od, sizeof od, hipMemcpyHostToDevice), "upload");
+  HIP_TRY(ctx, ctx->norm.reserve(2 * sizeof(float)), "allocate");
+  if (stats_dev)
+    HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
+  const int64_t nblocks = (nsamp + bs - 1) / bs;
+  HIP_TRY(ctx, launch_downsample(t1.as<SeriesDev>(), 1, t2.as<OctaveDev>(), ctx->norm.as<float>(),
+                                 dtype, out_dev, dtype, nblocks, bs, halo, st),
+          "downsample kernel");
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  return FFA_OK;
+}
+
+ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  if (!ctx->flag.ptr) return FFA_OK;
+  int32_t f = 0;
+  HIP_TRY(ctx, hipMemcpy(&f, ctx->flag.ptr, sizeof f, hipMemcpyDeviceToHost), "read flag");
+  HIP_TRY(ctx, launch_clear_flag(ctx->flag.as<int32_t>(), st), "clear flag");
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  if (f) return fail(ctx, FFA_ERR_DEGENERATE, "a normalised series had zero or non-finite variance");
+  return FFA_OK;
+}
+
+ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out) {
+  if (!ctx || !out) return FFA_ERR_INVALID_ARG;
+  out->lds_rows = ctx->tiling.lds_rows;
+  out->levels_per_pass = ctx->tiling.levels_per_pass;
+  return FFA_OK;
+}
+
+ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* t) {
+  if (!ctx || !t) return FFA_ERR_INVALID_ARG;
+  if (t->lds_rows < 0 || (t->lds_rows > 0 && t->lds_rows < 16) || t->levels_per_pass < 1 ||
+      t->levels_per_pass > kMaxRangeLevels)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4");
+  ctx->tiling.lds_rows = t->lds_rows;
+  ctx->tiling.levels_per_pass = t->levels_per_pass;
+  return FFA_OK;
+}
+
+ffa_status ffa_set_timing(ffa_ctx* ctx, int32_t enable) {
+  if (!ctx || (enable != 0 && enable != 1)) return FFA_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return FFA_OK;
+}
+
+ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset) {
+  if (!ctx || !out) return FFA_ERR_INVALID_ARG;
+  for (const TimedLaunch& t : ctx->pending) {
+    HIP_TRY(ctx, hipEventSynchronize(t.stop), "synchronise timing event");
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, t.start, t.stop), "read timing event");
+    if (t.kind == 0) {
+      ctx->times.stats_ms += ms;
+      ctx->times.stats_launches += 1;
+    } else if (t.kind == 1) {
+      ctx->times.downsample_ms += ms;
+      ctx->times.downsample_launches += 1;
+    } else {
+      ctx->times.fold_ms += ms;
+      ctx->times.fold_launches += 1;
+    }
+    ctx->event_pool.push_back(t.start);
+    ctx->event_pool.push_back(t.stop);
+  }
+  ctx->pending.clear();
+  *out = ctx->times;
+  if (reset) ctx->times = ffa_kernel_times{};
+  return FFA_OK;
+}
+
+ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series,
+                        const int64_t* nsamp, const ffa_search_params* params,
+                        const char* cache_path, ffa_tiling* best, void* stream) {
+  (void)ctx;
+  (void)nseries;
+  (void)series;
+  (void)nsamp;
+  (void)params;
+  (void)cache_path;
+  (void)best;
+  (void)stream;
+  return FFA_ERR_NOT_IMPLEMENTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Launchers of the HIP kernels of the FFA search.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ffa_internal.hpp"
+
+namespace ffa {
+
+// One input series of a launch.
+struct SeriesDev {
+  const void* ptr;    // raw samples (DEVICE)
+  int64_t nsamp;
+  int64_t chunk0;     // first downsampling block of this series
+  int32_t oct0;       // first octave of this series in the octave table
+  int32_t noct;
+  int32_t normalise;
+  int32_t halo;       // samples past a block needed by its last window
+};
+
+// One pseudo-octave of one series: where its downsampled samples go.
+struct OctaveDev {
+  uint64_t ds_fx;
+  int64_t nsamp;      // downsampled samples
+  int64_t off;        // element offset in the downsampled buffer
+};
+
+// Normalisation statistics of each series (Sec. 5.2), FP64:
+// stats[2i] = mean, stats[2i+1] = population standard deviation.
+// norm[2i] = mean, norm[2i+1] = 1 / std as FP32 for the downsampler.
+// partials holds blocks_per_series * nseries * 2 doubles. flag |= 1 when a
+// normalised series has zero or non-finite variance.
+hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dtype,
+                        int32_t blocks_per_series, double* partials, double* stats, float* norm,
+                        int32_t* flag, hipStream_t stream);
+
+// All pseudo-octaves of every series in one pass over the raw samples
+// (Sec. 5.3, App. A.4). nblocks = total downsampling blocks of the launch.
+hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
+                             const float* norm, int32_t dtype, void* out, int32_t out_dtype,
+                             int64_t nblocks, int32_t block_samples, int32_t max_halo,
+                             hipStream_t stream);
+
+// Downsampling block length for a given largest halo.
+int32_t downsample_block_samples(int32_t max_halo);
+
+// One pass of folding-transform tiles (Sec. 2.2), with the boxcar S/N of
+// final rows (Sec. 5.4).
+hipError_t launch_pass(const PassArgs& args, hipStream_t stream);
+
+// LDS bytes a pass launch uses.
+int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p);
+
+// Sets a flag word to zero with a kernel (graph-capture friendly).
+hipError_t launch_clear_flag(int32_t* flag, hipStream_t stream);
+
+}  // namespace ffa

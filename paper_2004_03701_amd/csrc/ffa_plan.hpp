@@ -1,0 +1,69 @@
+// Host-side period plan and tile plan of the FFA search.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ffa.h"
+#include "ffa_internal.hpp"
+
+namespace ffa {
+
+// One pseudo-octave (Sec. 5.3): the original series downsampled by
+// ds = ds_fx / 2^32.
+struct Octave {
+  double ds;         // factor before quantisation
+  uint64_t ds_fx;    // 32.32 fixed point
+  double tau;        // sampling time after downsampling
+  int64_t nsamp;     // downsampled samples
+  double var;        // noise variance of a downsampled sample (App. A.4)
+  int64_t ds_off;    // offset of this octave in the series' downsampled buffer
+};
+
+// One folding transform: bins p, m rows of the octave's series.
+struct Transform {
+  int32_t octave, p, m, keep;
+  int64_t row0;      // periodogram row of s = 0
+};
+
+struct SeriesPlan {
+  std::vector<Octave> oct;
+  std::vector<Transform> tr;
+  int64_t rows = 0;        // kept periodogram rows
+  int64_t ds_total = 0;    // samples of all octaves
+  uint64_t ds_fx_max = 0;
+  int64_t cells = 0;       // sum of m * p over transforms
+};
+
+// Validates params and nsamp and builds the plan. Returns FFA_OK or an error
+// status with a message in *err.
+ffa_status build_series_plan(const ffa_search_params& params, int64_t nsamp, SeriesPlan* out,
+                             std::string* err);
+
+// Validates the parameters alone (no nsamp).
+ffa_status validate_params(const ffa_search_params& params, std::string* err);
+
+// Trial period of row s of an m-row transform (Eq. for P_s, Sec. 2.3).
+double trial_period(int64_t s, int64_t m, int64_t p, double tau);
+
+// Tile shapes.
+struct Tiling {
+  int32_t lds_rows = 0;         // 0: the largest that fits
+  int32_t levels_per_pass = 4;  // 1..kMaxRangeLevels
+};
+
+// Rows of a p-bin profile tile that fit in one workgroup's LDS.
+int32_t rows_capacity(int32_t p, const Tiling& t);
+
+// Tiles of one transform, grouped by pass. `xf` is the transform's index in
+// the launch's transform table. Appends to passes[k] for pass k.
+void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
+                          int32_t levels_per_pass, bool out_rows,
+                          std::vector<std::vector<TileDesc>>* passes);
+
+// Start row and size of node `node` at depth d of the m-row tree.
+void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n);
+
+}  // namespace ffa

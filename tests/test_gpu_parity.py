@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: the folding transform is bit-exact on integer-valued inputs (every FP32
+partial sum is then an exact integer); S/N agrees within
+1e-4 * max(1, |oracle|) in FP32; statistics and downsampling within stated
+FP32/FP64 rounding bounds.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2004_03701_amd as ffa  # noqa: E402
+
+SNR_RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = ffa.ffa_create(0)
+    yield c
+    ffa.ffa_destroy(c)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def snr_close(gpu, ref, rtol=SNR_RTOL):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    err = np.abs(gpu - ref) / np.maximum(1.0, np.abs(ref))
+    return float(err.max()) if err.size else 0.0
+
+
+# ---------------------------------------------------------------------------
+# Folding transform, bit-exact on integers
+# ---------------------------------------------------------------------------
+
+TRANSFORM_SHAPES = [
+    (1, 7), (2, 2), (2, 3), (3, 5), (5, 17), (8, 6), (37, 128), (64, 255), (100, 259),
+    (129, 259), (130, 259), (131, 259), (257, 240), (1000, 251), (1073, 259), (1310, 200),
+    (2048, 128), (3001, 97), (12000, 33), (500, 1000), (300, 1280), (41, 2),
+]
+
+
+@pytest.mark.parametrize("m,p", TRANSFORM_SHAPES)
+def test_transform_bit_exact_on_integers(ctx, m, p):
+    print(f"transform m={m} p={p}", flush=True)
+    g = np.random.default_rng(1000 * m + p)
+    X = g.integers(-8, 9, size=(m, p)).astype(np.float64)
+    ref = oracle.fold_ffa(X)
+    out = ffa.ffa_transform(ctx, dev(X))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("lds_rows,levels", [(16, 1), (16, 2), (24, 3), (40, 4), (0, 2)])
+def test_transform_tilings_agree(ctx, lds_rows, levels):
+    m, p = 1500, 61
+    g = np.random.default_rng(7)
+    X = g.integers(-8, 9, size=(m, p)).astype(np.float64)
+    ref = oracle.fold_ffa(X)
+    ffa.ffa_set_tiling(ctx, lds_rows, levels)
+    try:
+        out = ffa.ffa_transform(ctx, dev(X))
+        torch.cuda.synchronize()
+    finally:
+        ffa.ffa_set_tiling(ctx, 0, 4)
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
+
+
+def test_transform_noise_fp32(ctx):
+    m, p = 1073, 259
+    X = np.random.default_rng(3).standard_normal((m, p)).astype(np.float32)
+    ref = oracle.fold_ffa(X.astype(np.float64))
+    out = ffa.ffa_transform(ctx, dev(X)).cpu().numpy()
+    # 11 FP32 additions per output: relative error well under 1e-5 of sqrt(m)
+    assert np.abs(out - ref).max() < 1e-5 * math.sqrt(m) * 4
+
+
+# ---------------------------------------------------------------------------
+# Statistics and downsampling
+# ---------------------------------------------------------------------------
+
+def test_series_stats(ctx):
+    x = (np.random.default_rng(4).standard_normal(1_000_003) * 3.0 + 17.0).astype(np.float32)
+    st = ffa.ffa_series_stats(ctx, dev(x)).cpu().numpy()
+    mu, sd = oracle.normalise_stats(x)
+    assert abs(st[0] - mu) < 1e-12 * abs(mu) + 1e-12
+    assert abs(st[1] - sd) < 1e-11 * sd
+
+
+@pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3])
+def test_downsample(ctx, ds):
+    n = 300_001
+    x = (np.random.default_rng(5).standard_normal(n) + 0.3).astype(np.float32)
+    ds_fx = int(math.floor(ds * 2 ** 32 + 0.5))
+    nout = (n << 32) // ds_fx
+    xd = dev(x)
+    st = ffa.ffa_series_stats(ctx, xd)
+    y = ffa.ffa_downsample(ctx, xd, ds_fx, nout, stats=st).cpu().numpy().astype(np.float64)
+    mu, sd = oracle.normalise_stats(x)
+    ref = oracle.downsample((x.astype(np.float64) - mu) / sd, ds_fx, nout)
+    # FP32 prefix over a block of <= 16K samples: error ~1e-5 absolute
+    assert np.abs(y - ref).max() < 2e-5 * max(1.0, math.sqrt(ds)) * 4
+
+
+# ---------------------------------------------------------------------------
+# Whole search
+# ---------------------------------------------------------------------------
+
+def run_search(ctx, x, cfg, normalise=True, dtype=ffa.FFA_F32, tdtype=torch.float32):
+    prm = ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min, cfg.bins_max,
+                          cfg.widths, normalise=normalise, dtype=dtype)
+    per, bins, snr = ffa.ffa_search(ctx, dev(x, tdtype), prm)
+    torch.cuda.synchronize()
+    return per, bins, snr.cpu().numpy()
+
+
+def test_search_small_multi_octave(ctx):
+    x = np.random.default_rng(6).standard_normal(20_000).astype(np.float32)
+    cfg = synth.SearchConfig(1.0, 40.0, 400.0, 40, 47, (1, 2, 3, 5, 8))
+    per, bins, snr = run_search(ctx, x, cfg)
+    ref = oracle.search(x, 1.0, 40.0, 400.0, 40, 47, cfg.widths)
+    assert np.array_equal(per, ref.periods) and np.array_equal(bins, ref.bins)
+    assert snr_close(snr, ref.snr) < SNR_RTOL
+
+
+def test_search_integer_series_matches_closely(ctx):
+    # integer samples, ds = 1, no normalisation: boxcar sums are exact
+    x = np.random.default_rng(8).integers(-8, 9, size=40_000).astype(np.float32)
+    cfg = synth.SearchConfig(1.0, 64.0, 128.0, 64, 127, (1, 2, 3, 4, 6, 9))
+    per, bins, snr = run_search(ctx, x, cfg, normalise=False)
+    ref = oracle.search(x, 1.0, 64.0, 128.0, 64, 127, cfg.widths, normalise=False)
+    assert snr_close(snr, ref.snr) < 1e-6
+
+
+def test_search_workload1_full(ctx):
+    x, cfg, pulses = synth.workload1()
+    per, bins, snr = run_search(ctx, x, cfg)
+    ref = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                        cfg.bins_max, cfg.widths)
+    assert np.array_equal(per, ref.periods)
+    assert snr_close(snr, ref.snr) < SNR_RTOL
+    # the injected pulse (period 200.37 samples, S/N 15) is the top peak
+    best = np.unravel_index(np.argmax(snr), snr.shape)
+    assert abs(per[best[0]] - pulses[0].period) < 0.01
+    assert snr.max() > 11.0
+
+
+def test_degenerate_series_sets_status(ctx):
+    x = np.full(20_000, 3.0, dtype=np.float32)
+    cfg = synth.SearchConfig(1.0, 40.0, 400.0, 40, 47, (1, 2))
+    _, _, snr = run_search(ctx, x, cfg)
+    assert np.isnan(snr).all()
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_ERR_DEGENERATE
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+
+
+def test_invalid_arguments_do_no_device_work(ctx):
+    x = dev(np.zeros(1000, np.float32))
+    prm = ffa.make_params(1.0, 40.0, 400.0, 40, 47, (1, 2))
+    snr = torch.zeros((3, 2), device="cuda")
+    with pytest.raises(ffa.FFAError) as e:
+        ffa.ffa_search(ctx, x, prm, snr=snr)
+    assert e.value.status == ffa.FFA_ERR_BUFFER_TOO_SMALL
+    assert "small" in ffa.ffa_last_error(ctx)
+    assert (snr == 0).all()
