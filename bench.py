@@ -43,6 +43,10 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def make_inputs(torch, nseries, nsamp):
     import synth
     x = torch.empty((nseries, nsamp), dtype=torch.float32, device="cuda")
@@ -53,6 +57,8 @@ def make_inputs(torch, nseries, nsamp):
     with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
         for i, s in ex.map(gen, range(nseries)):
             x[i].copy_(torch.from_numpy(s))
+            if (i + 1) % 64 == 0:
+                log(f"generated {i + 1}/{nseries} series")
     torch.cuda.synchronize()
     return x
 
@@ -112,6 +118,7 @@ def main():
     ctx = ffa.ffa_create(0)
     results = {}
     for v in variants:
+        log(f"variant {v}")
         dt_code, tdt = store[v]
         xs = x32 if tdt is None else lowp(torch, x32, tdt)
         series = [xs[i] for i in range(a.series)]
@@ -125,6 +132,7 @@ def main():
         for _ in range(a.warmup):
             ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
         torch.cuda.synchronize()
+        log(f"variant {v}: warm-up done, timing {a.steps} steps")
         ffa.ffa_set_timing(ctx, not a.graph)
         ffa.ffa_read_timing(ctx, reset=True)
         torch.cuda.synchronize()
@@ -181,6 +189,7 @@ def main():
     if "f32" in results and head != "f32":
         out["speedup_vs_f32"] = results[head]["profiles_per_s"] / results["f32"]["profiles_per_s"]
     if a.cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds, nsamp)
     ffa.ffa_destroy(ctx)
     print(json.dumps(out), flush=True)

@@ -87,8 +87,7 @@ struct Job {
   int32_t max_p = 0;
   int32_t widths[kMaxWidths] = {0};
   bool any_normalise = false;
-  int32_t max_halo = 0;
-  int32_t block_samples = 0;
+  int32_t ds_lds_floats = 0;
   int64_t ds_blocks = 0;
   int64_t ds_total = 0;     // elements of the downsampled buffer
   int64_t scr_cells = 0;    // floats per scratch buffer
@@ -127,6 +126,7 @@ struct ffa_ctx {
   std::map<std::string, std::shared_ptr<Job>> jobs;
   std::map<std::string, std::shared_ptr<GraphEntry>> graphs;
   DevBuf ds_buf, scr0, scr1, stats, norm, partials, flag, tune_out;
+  DevBuf full_ht, full_rot, full_off;  // merge schedules of full subtrees
   size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
 };
 
@@ -193,11 +193,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   std::vector<XformDesc> xf;
   std::vector<float> scales;
   int64_t ds_off = 0, chunk = 0;
-  int32_t max_halo = 0;
-  for (int i = 0; i < nseries; ++i)
-    max_halo = std::max<int32_t>(max_halo, (int32_t)(plans[i]->ds_fx_max >> 32) + 2);
-  job->max_halo = max_halo;
-  job->block_samples = downsample_block_samples(max_halo);
+  job->ds_lds_floats = 0;
   // transforms grouped so that each group's scratch fits the budget
   struct GroupSpan {
     size_t xf0, xf1;
@@ -215,9 +211,14 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     sd[i].oct0 = (int32_t)od.size();
     sd[i].noct = (int32_t)pl.oct.size();
     sd[i].normalise = a.normalise;
-    sd[i].halo = max_halo;
+    // block length from the series' own plan, so that its downsampled samples
+    // do not depend on the other series of the batch
+    sd[i].halo = (int32_t)(pl.ds_fx_max >> 32) + 2;
+    sd[i].block = downsample_block_samples(sd[i].halo);
+    sd[i].pad = 0;
+    job->ds_lds_floats = std::max<int32_t>(job->ds_lds_floats, 2 * (sd[i].block + sd[i].halo) + 2);
     if (a.normalise) job->any_normalise = true;
-    chunk += (nsamp[i] + job->block_samples - 1) / job->block_samples;
+    chunk += (nsamp[i] + sd[i].block - 1) / sd[i].block;
     for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
     if ((size_t)(gcells + pl.cells) > ctx->scratch_budget_cells && gcells > 0) {
       spans.push_back(GroupSpan{gx0, xf.size(), gcells});
@@ -300,6 +301,12 @@ ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
   return FFA_OK;
 }
 
+void set_schedules(ffa_ctx* ctx, PassArgs* pa) {
+  pa->full_ht = ctx->full_ht.as<uint32_t>();
+  pa->full_rot = ctx->full_rot.as<uint16_t>();
+  pa->full_off = ctx->full_off.as<int32_t>();
+}
+
 hipError_t take_event(ffa_ctx* ctx, hipEvent_t* ev) {
   if (!ctx->event_pool.empty()) {
     *ev = ctx->event_pool.back();
@@ -349,7 +356,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   TimedScope ts(ctx, 1, stream, timed);
   HIP_TRY(ctx, launch_downsample(sd, job.nseries, job.oct.as<OctaveDev>(), ctx->norm.as<float>(),
                                  job.dtype, ctx->ds_buf.ptr, job.dtype, job.ds_blocks,
-                                 job.block_samples, job.max_halo, stream),
+                                 job.ds_lds_floats, stream),
           "downsample kernel");
   }
   PassArgs pa{};
@@ -366,6 +373,8 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   for (int q = 0; q < kMaxWidths; ++q) pa.widths[q] = job.widths[q];
   pa.wmax = job.wmax;
   pa.max_p = job.max_p;
+  pa.width_set = width_set_of(job.widths, job.num_widths);
+  set_schedules(ctx, &pa);
   const TileDesc* tiles = job.tiles.as<TileDesc>();
   for (const Group& g : job.groups) {
     for (const Launch& l : g.passes) {
@@ -482,6 +491,15 @@ ffa_status ffa_create(int device, ffa_ctx** out) {
   ffa_ctx* c = new (std::nothrow) ffa_ctx();
   if (!c) return FFA_ERR_NOMEM;
   c->device = device;
+  std::vector<uint32_t> ht;
+  std::vector<uint16_t> rot;
+  std::vector<int32_t> off;
+  build_full_schedules(&ht, &rot, &off);
+  if (upload(c->full_ht, ht) != hipSuccess || upload(c->full_rot, rot) != hipSuccess ||
+      upload(c->full_off, off) != hipSuccess) {
+    delete c;
+    return FFA_ERR_DEVICE;
+  }
   *out = c;
   return FFA_OK;
 }
@@ -624,6 +642,8 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   pa.widths[0] = 1;
   pa.wmax = 1;
   pa.max_p = p;
+  pa.width_set = kWidthsGeneral;
+  set_schedules(ctx, &pa);
   pa.scr0 = ctx->scr0.as<float>();
   pa.scr1 = ctx->scr1.as<float>();
   pa.out_rows = out;
@@ -645,7 +665,7 @@ ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int
   if (dtype != FFA_F32 && dtype != FFA_BF16 && dtype != FFA_F16)
     return fail(ctx, FFA_ERR_INVALID_ARG, "unknown dtype");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SeriesDev sd{series, nsamp, 0, 0, 0, 1, 0};
+  SeriesDev sd{series, nsamp, 0, 0, 0, 1, 0, 0, 0};
   DevBuf tmp;
   HIP_TRY(ctx, tmp.reserve(sizeof(SeriesDev)), "allocate");
   HIP_TRY(ctx, hipMemcpy(tmp.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
@@ -676,7 +696,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t halo = (int32_t)(ds_fx >> 32) + 2;
   const int32_t bs = downsample_block_samples(halo);
-  SeriesDev sd{series, nsamp, 0, 0, 1, stats_dev ? 1 : 0, halo};
+  SeriesDev sd{series, nsamp, 0, 0, 1, stats_dev ? 1 : 0, halo, bs, 0};
   OctaveDev od{ds_fx, nout, 0};
   DevBuf t1, t2;
   HIP_TRY(ctx, t1.reserve(sizeof sd), "allocate");
@@ -688,7 +708,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
     HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
   const int64_t nblocks = (nsamp + bs - 1) / bs;
   HIP_TRY(ctx, launch_downsample(t1.as<SeriesDev>(), 1, t2.as<OctaveDev>(), ctx->norm.as<float>(),
-                                 dtype, out_dev, dtype, nblocks, bs, halo, st),
+                                 dtype, out_dev, dtype, nblocks, 2 * (bs + halo) + 2, st),
           "downsample kernel");
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
   return FFA_OK;

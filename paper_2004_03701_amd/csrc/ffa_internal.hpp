@@ -6,42 +6,53 @@
 
 namespace ffa {
 
-// Columns handled by one merge item. Odd, so that 64 lanes reading
-// consecutive items hit 64 distinct LDS banks.
+// Consecutive columns a lane merges per row (odd, so that the 64 lanes of a
+// wave reading consecutive column groups hit distinct LDS banks).
 constexpr int kChunk = 5;
 // Threads of a search-kernel workgroup (16 waves of 64).
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
-// Merge items a thread stages in registers per level (rows x chunks of a
-// tile must not exceed kItemsMax * kThreads).
-constexpr int kItemsMax = 8;
+// (row, column-group) slots a lane stages in registers per merge level.
+constexpr int kStageMax = 8;
+// Largest subtree a full tile folds; the host precomputes their schedules.
+constexpr int kMaxFullRows = 192;
 // Largest number of boxcar widths and of bins per profile.
 constexpr int kMaxWidths = 32;
 constexpr int kMaxBins = 1280;
-constexpr int kSnrColsMax = (kMaxBins + 63) / 64;  // phases per lane in the S/N step
+constexpr int kSnrColsMax = (kMaxBins + 63) / 64;  // phases per lane, general S/N path
 // Largest number of merge levels in one range pass (2^L source nodes).
 constexpr int kMaxRangeLevels = 4;
 constexpr int kMetaNodes = (2 << kMaxRangeLevels) - 1;
 // LDS available to one search workgroup (gfx950: 160 KiB per CU).
 constexpr int kLdsBytes = 160 * 1024;
-// LDS set aside for the S/N prefix arrays of the waves.
-constexpr int kSnrLdsBytes = 24 * 1024;
+// LDS set aside for the S/N step.
+constexpr int kSnrLdsBytes = 10 * 1024;
 
-// Row stride in LDS (floats) of a profile of p bins: the row is followed by a
-// copy of its first kChunk - 1 bins, so a rotated read of kChunk consecutive
-// bins starting below p never wraps.
-inline __host__ __device__ int lds_stride(int p) { return p + kChunk - 1; }
+// Row stride in LDS (floats) of a profile of p bins. Bins p .. p + kChunk - 2
+// hold a copy of bins 0 .. kChunk - 2, so a rotated read of kChunk consecutive
+// bins starting below p never wraps. The stride covers every kChunk-column
+// group that starts below p + kChunk - 1 (those groups then compute the copy
+// themselves) and is odd, so lanes reading the same column of different rows
+// hit different banks.
+inline __host__ __device__ int merge_groups(int p) {
+  return (p + kChunk - 1 + kChunk - 1) / kChunk;
+}
+inline __host__ __device__ int lds_stride(int p) { return (merge_groups(p) * kChunk) | 1; }
+
+// Column groups per lane for a p-bin row (one wave covers a row).
+inline __host__ __device__ int col_iters(int p) { return (merge_groups(p) + 63) / 64; }
 
 // Rows of a p-bin profile tile that fit in one workgroup's LDS next to the
-// merge tables, the range-tile metadata and the S/N prefix arrays; at most
+// merge tables, the range-tile metadata, the S/N arrays, an all-zero row (the
+// tail of plain copies) and a junk row (target of idle slots' writes); at most
 // `cap` when cap > 0.
 inline __host__ __device__ int rows_capacity(int p, int cap) {
-  const int fixed = kSnrLdsBytes + kMetaNodes * 5 * 4 + 64;
+  const int fixed = kSnrLdsBytes + kMetaNodes * 5 * 4 + 64 + 2 * lds_stride(p) * 4;
   const int per_row = lds_stride(p) * 4 + 3 * 4;
   int r = (kLdsBytes - fixed) / per_row;
-  const int nch = (p + kChunk - 1) / kChunk;
-  const int ri = (kItemsMax * kThreads) / nch;
-  r = r < ri ? r : ri;
+  const int rs = kWaves * (kStageMax / col_iters(p));
+  r = r < rs ? r : rs;
+  r = r < kMaxFullRows ? r : kMaxFullRows;
   if (cap > 0 && cap < r) r = cap;
   return r < 2 ? 2 : r;
 }
@@ -92,7 +103,23 @@ struct PassArgs {
   const float* scales;     // per transform and width: 1 / sqrt(m w var)
   int32_t widths[kMaxWidths];
   int32_t wmax;
-  int32_t max_p;           // largest p of the launch (sizes the S/N LDS arrays)
+  int32_t max_p;           // largest p of the launch
+  int32_t width_set;       // 0: general widths; else a compiled width grid (WidthSet)
+  // Merge schedules of full subtrees of n rows (2 <= n <= kMaxFullRows):
+  // entry full_off[n] + lev * n + q gives, for row q at relative depth lev,
+  // the head row (low 16 bits) and tail row (high 16 bits; 0xffff: the row
+  // is a one-row block and stays) and the rotation s - j.
+  const uint32_t* full_ht;
+  const uint16_t* full_rot;
+  const int32_t* full_off;
+};
+
+// Width grids the S/N step is compiled for (registers instead of LDS for the
+// prefix history).
+enum WidthSet : int32_t {
+  kWidthsGeneral = 0,
+  kWidthsPaper9 = 1,   // 1,2,3,4,6,9,13,19,28: w0 = 1, w_{k+1} = max(floor(1.5 w_k), w_k + 1)
+  kWidthsDuty9 = 2,    // 1,2,3,5,8,12,19,30,48: duty cycles 0.5 % .. 20 % of 240 bins
 };
 
 }  // namespace ffa

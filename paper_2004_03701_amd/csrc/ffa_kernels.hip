@@ -189,12 +189,21 @@ __global__ void k_norm_from_stats(const double* stats, float* norm) {
 
 constexpr int kDsThreads = 512;
 
+// Smallest j with j * ds_fx >= x_fx (all in 2^-32 samples): a double-precision
+// estimate, then exact integer fix-ups.
+__device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
+  int64_t j = (int64_t)ceil((double)x_fx / (double)ds_fx);
+  if (j < 0) j = 0;
+  while (j > 0 && (uint64_t)(j - 1) * ds_fx >= x_fx) --j;
+  while ((uint64_t)j * ds_fx < x_fx) ++j;
+  return j;
+}
+
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
                                                            int32_t nseries,
                                                            const OctaveDev* oct,
                                                            const float* norm, int dtype,
-                                                           void* out, int out_dtype,
-                                                           int32_t block_samples) {
+                                                           void* out, int out_dtype) {
   extern __shared__ float sm[];
   __shared__ int s_series;
   __shared__ float s_part[kDsThreads];
@@ -213,9 +222,9 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   __syncthreads();
   const int si = s_series;
   const SeriesDev sd = series[si];
-  const int64_t c0 = ((int64_t)blockIdx.x - sd.chunk0) * block_samples;
+  const int64_t c0 = ((int64_t)blockIdx.x - sd.chunk0) * sd.block;
   if (c0 >= sd.nsamp) return;
-  const int64_t c1 = min(c0 + (int64_t)block_samples, sd.nsamp);
+  const int64_t c1 = min(c0 + (int64_t)sd.block, sd.nsamp);
   const int64_t cend = min(sd.nsamp, c1 + (int64_t)sd.halo);
   const int len = (int)(cend - c0);
   float* xs = sm;                 // len samples
@@ -247,9 +256,12 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   for (int k = 0; k < sd.noct; ++k) {
     const OctaveDev o = oct[sd.oct0 + k];
     if (o.nsamp == 0) continue;
-    const int64_t j0 = (int64_t)((lo_fx + o.ds_fx - 1) / o.ds_fx);
-    const int64_t j1 = min((int64_t)((hi_fx + o.ds_fx - 1) / o.ds_fx), o.nsamp);
-    for (int64_t j = j0 + tid; j < j1; j += kDsThreads) {
+    // outputs whose window starts in [c0, c1): j in [ceil(c0 / ds), ceil(c1 / ds))
+    const int64_t j0 = first_window(lo_fx, o.ds_fx);
+    const int64_t j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
+    const int nj = (int)(j1 - j0);
+    for (int r = tid; r < nj; r += kDsThreads) {
+      const int64_t j = j0 + r;
       const uint64_t a = (uint64_t)j * o.ds_fx, b = a + o.ds_fx;
       const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
       const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
@@ -284,9 +296,20 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void merge_indices(int n, int s, int& i, int& j) {
-  const int64_t mh = n >> 1, mt = n - mh, den = 2 * (int64_t)(n - 1);
-  i = (int)((2 * (mh - 1) * s + (n - 1)) / den);
-  j = (int)((2 * (mt - 1) * s + (n - 1)) / den);
+  // nint(a / c) with ties up is floor((2a + c) / (2c)); a double-precision
+  // quotient, then an exact integer fix-up
+  const int mh = n >> 1, mt = n - mh;
+  const int64_t den = 2 * (int64_t)(n - 1);
+  const int64_t ni = 2 * (int64_t)(mh - 1) * s + (n - 1);
+  const int64_t nj = 2 * (int64_t)(mt - 1) * s + (n - 1);
+  const double rd = 1.0 / (double)den;
+  int64_t qi = (int64_t)((double)ni * rd), qj = (int64_t)((double)nj * rd);
+  if (qi * den > ni) --qi;
+  if ((qi + 1) * den <= ni) ++qi;
+  if (qj * den > nj) --qj;
+  if ((qj + 1) * den <= nj) ++qj;
+  i = (int)qi;
+  j = (int)qj;
 }
 
 __device__ __forceinline__ void node_geometry(int m, int d, int node, int& r0, int& n) {
@@ -310,64 +333,142 @@ __device__ __forceinline__ int ceil_log2(int n) {
   return l;
 }
 
-// Item index -> (row, chunk) with a float reciprocal and an exact fix-up.
-__device__ __forceinline__ void split_item(int it, int nch, float rnch, int& q, int& c) {
-  q = (int)((float)it * rnch);
-  if (q * nch > it) --q;
-  if ((q + 1) * nch <= it) ++q;
-  c = it - q * nch;
+// Slot <-> (row of the wave, column iteration) mapping shared by the load,
+// merge and store phases: slot = r * J + j, row q = wave + 16 r, column
+// group lane + 64 j. JS = 1 fixes J = 1 at compile time (p <= 320).
+template <int JS>
+struct Slots {
+  int J;
+  __device__ __forceinline__ int row(int slot) const { return JS == 1 ? slot : slot / J; }
+  __device__ __forceinline__ int iter(int slot) const { return JS == 1 ? 0 : slot - (slot / J) * J; }
+};
+
+// The operation of one output row of a merge level, held by lane r of a wave
+// for the wave's row r: output <- row h + (row t << rot). Plain copies (and
+// one-row blocks, which stay) add the all-zero row.
+struct LaneOp {
+  int h, t, rot;
+};
+
+// One merge level, in place, for waves whose rows fit in NS slots: a wave
+// takes output rows wave, wave + 16, ...; lane l owns the column groups
+// l, l + 64, ... of kChunk columns. All reads of a lane are issued first, the
+// workgroup synchronises, then the outputs are written back. Groups that
+// start past p compute the row's wrapped copy; lanes and slots with nothing
+// to write send their values to the junk row, so no step branches.
+template <int JS, int NS>
+__device__ __forceinline__ void merge_level_ns(float* rows, int p, int stride, int J,
+                                               const LaneOp& op, float* junk, int nrw) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const Slots<JS> sl{J};
+  float acc[NS][kChunk];
+#pragma unroll
+  for (int slot = 0; slot < NS; ++slot) {
+    const int r = sl.row(slot);
+    const int h = __builtin_amdgcn_readlane(op.h, r);
+    const int tl = __builtin_amdgcn_readlane(op.t, r);
+    const int rot = __builtin_amdgcn_readlane(op.rot, r);
+    const int col0 = (lane + 64 * sl.iter(slot)) * kChunk;
+    int t0 = col0 + rot;
+    t0 = t0 >= p ? t0 - p : t0;
+    if (p < kChunk - 1) t0 %= p;  // rows shorter than the copy
+    const float* hr = rows + h * stride + col0;
+    const float* trow = rows + tl * stride + t0;
+#pragma unroll
+    for (int e = 0; e < kChunk; ++e) acc[slot][e] = hr[e] + trow[e];
+  }
+  __syncthreads();
+  const int G = merge_groups(p);
+#pragma unroll
+  for (int slot = 0; slot < NS; ++slot) {
+    const int r = sl.row(slot);
+    const int c = lane + 64 * sl.iter(slot);
+    float* o = (r < nrw && c < G) ? rows + (wave + kWaves * r) * stride + c * kChunk : junk;
+#pragma unroll
+    for (int e = 0; e < kChunk; ++e) o[e] = acc[slot][e];
+  }
+  __syncthreads();
 }
 
-// One merge level: output position q takes row th[q] plus row tt[q] rotated
-// left by tr[q] (tt[q] == -1: plain copy of row th[q]; -2: nothing to do).
-__device__ __forceinline__ void merge_level(float* rows, const int* th, const int* tt,
-                                            const int* tr, int count, int p, int stride,
-                                            int nch, float rnch) {
-  float acc[kItemsMax][kChunk];
-  const int items = count * nch;
+template <int JS>
+__device__ __forceinline__ void merge_level(float* rows, int count, int p, int stride, int J,
+                                            const LaneOp& op, float* junk) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  const int need = nrw * J;
+  if (need <= 4)
+    merge_level_ns<JS, 4>(rows, p, stride, J, op, junk, nrw);
+  else if (need <= 8)
+    merge_level_ns<JS, 8>(rows, p, stride, J, op, junk, nrw);
+  else
+    merge_level_ns<JS, kStageMax>(rows, p, stride, J, op, junk, nrw);
+}
+
+// Loads rows [0, count) into LDS with their wrapped copies; lane r of each
+// wave holds in `src` the element offset of the wave's row r. Lanes take
+// consecutive columns (coalesced), four rows at a time.
+template <int DT>
+__device__ __forceinline__ void load_rows(float* rows, int count, int p, int stride,
+                                          const void* base, int64_t src) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  const int width = p + kChunk - 1;
+  const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
+  for (int rb = 0; rb < nrw; rb += 4) {
+    int64_t g[4];
 #pragma unroll
-  for (int k = 0; k < kItemsMax; ++k) {
-    const int it = threadIdx.x + k * kThreads;
-    if (it < items) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      const int tl = tt[q];
-      if (tl != -2) {
-        const float* hr = rows + th[q] * stride + c * kChunk;
-        if (tl < 0) {
+    for (int u = 0; u < 4; ++u)
+      g[u] = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, min(rb + u, 63)) |
+             ((int64_t)__builtin_amdgcn_readlane(hi, min(rb + u, 63)) << 32);
+    for (int c0 = 0; c0 < width; c0 += 128) {
+      float v[4][2];
 #pragma unroll
-          for (int e = 0; e < kChunk; ++e) acc[k][e] = hr[e];
-        } else {
-          int t0 = c * kChunk + tr[q];
-          if (t0 >= p) t0 -= p;
-          const float* trow = rows + tl * stride + t0;
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int e = 0; e < kChunk; ++e) acc[k][e] = hr[e] + trow[e];
+        for (int k = 0; k < 2; ++k) {
+          const int c = c0 + lane + 64 * k;
+          int col = c < p ? c : c - p;
+          if (col >= p) col %= p;  // rows shorter than the copy
+          v[u][k] = (rb + u < nrw && c < width) ? load_sample(base, DT, g[u] + col) : 0.0f;
         }
-      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int c = c0 + lane + 64 * k;
+          if (rb + u < nrw && c < width) rows[(wave + kWaves * (rb + u)) * stride + c] = v[u][k];
+        }
     }
   }
-  __syncthreads();
+}
+
+// Writes rows [0, count) of LDS to global rows dst + q * p, coalesced.
+__device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
+                                           float* dst) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  for (int rb = 0; rb < nrw; rb += 4) {
+    for (int c0 = 0; c0 < p; c0 += 128) {
+      float v[4][2];
 #pragma unroll
-  for (int k = 0; k < kItemsMax; ++k) {
-    const int it = threadIdx.x + k * kThreads;
-    if (it < items) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      if (tt[q] != -2) {
-        float* o = rows + q * stride;
-        const int col0 = c * kChunk;
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int e = 0; e < kChunk; ++e)
-          if (col0 + e < p) o[col0 + e] = acc[k][e];
-        if (c == 0) {
-#pragma unroll
-          for (int e = 0; e < kChunk - 1; ++e) o[p + e] = acc[k][e];
+        for (int k = 0; k < 2; ++k) {
+          const int c = c0 + lane + 64 * k;
+          v[u][k] = (rb + u < nrw && c < p) ? rows[(wave + kWaves * (rb + u)) * stride + c] : 0.0f;
         }
-      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int c = c0 + lane + 64 * k;
+          if (rb + u < nrw && c < p) dst[(int64_t)(wave + kWaves * (rb + u)) * p + c] = v[u][k];
+        }
     }
   }
-  __syncthreads();
 }
 
 // Range-tile metadata: node h of the tile's subtree (heap order, level l holds
@@ -381,17 +482,21 @@ struct Meta {
   int* off;
 };
 
-__device__ void build_meta(Meta M, int r0, int n, int s0, int s1, int L) {
-  M.r0[0] = r0;
-  M.n[0] = n;
-  M.lo[0] = s0;
-  M.hi[0] = s1;
-  M.off[0] = 0;
+// Built by wave 0: lane v handles node v of a level.
+__device__ __forceinline__ void build_meta(Meta M, int r0, int n, int s0, int s1, int L) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) {
+    M.r0[0] = r0;
+    M.n[0] = n;
+    M.lo[0] = s0;
+    M.hi[0] = s1;
+    M.off[0] = 0;
+  }
+  wave_lds_sync();
   for (int l = 0; l < L; ++l) {
-    const int first = (1 << l) - 1, cfirst = (2 << l) - 1;
-    int off = 0;
-    for (int v = 0; v < (1 << l); ++v) {
-      const int h = first + v, hc = cfirst + 2 * v;
+    const int cfirst = (2 << l) - 1;
+    if (lane < (1 << l)) {
+      const int h = (1 << l) - 1 + lane, hc = cfirst + 2 * lane;
       const int pn = M.n[h], plo = M.lo[h], phi = M.hi[h];
       if (phi <= plo || pn == 0) {
         M.r0[hc] = M.r0[hc + 1] = M.r0[h];
@@ -419,11 +524,12 @@ __device__ void build_meta(Meta M, int r0, int n, int s0, int s1, int L) {
         M.lo[hc + 1] = j0;
         M.hi[hc + 1] = j1 + 1;
       }
-      M.off[hc] = off;
-      off += M.hi[hc] - M.lo[hc];
-      M.off[hc + 1] = off;
-      off += M.hi[hc + 1] - M.lo[hc + 1];
     }
+    wave_lds_sync();
+    const int len = lane < (2 << l) ? M.hi[cfirst + lane] - M.lo[cfirst + lane] : 0;
+    const int incl = wave_inclusive_sum(len, lane);
+    if (lane < (2 << l)) M.off[cfirst + lane] = incl - len;
+    wave_lds_sync();
   }
 }
 
@@ -435,178 +541,112 @@ __device__ __forceinline__ int find_node(const Meta& M, int l, int q) {
   return first + v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const TileDesc t = a.tiles[blockIdx.x];
-  const XformDesc x = a.xf[t.xf];
-  const int p = x.p, stride = lds_stride(p), nch = (p + kChunk - 1) / kChunk;
-  const float rnch = 1.0f / (float)nch;
-  const int R = rows_capacity(p, a.lds_rows_cap);
-  float* rows = reinterpret_cast<float*>(smem);
-  int* th = reinterpret_cast<int*>(rows + R * stride);
-  int* tt = th + R;
-  int* tr = tt + R;
-  Meta M{tr + R, tr + R + kMetaNodes, tr + R + 2 * kMetaNodes, tr + R + 3 * kMetaNodes,
-         tr + R + 4 * kMetaNodes};
-  float* snrbuf = reinterpret_cast<float*>(tr + R + 5 * kMetaNodes);
-  const int tid = threadIdx.x;
+// ---------------------------------------------------------------------------
+// Boxcar S/N of final rows (Sec. 5.4). For a profile P of p bins, the boxcar
+// of width w starting at bin n sums S[n + w] - S[n], S the exclusive prefix
+// sum over two repeats of P; the S/N is the best sum over n times
+// 1 / sqrt(m w var) (precomputed in FP64).
+//
+// Compiled width grids: lane = row, and the wave walks the bins of its rows
+// in step, keeping the last wmax + 1 prefix sums in a register ring, so each
+// step costs one LDS read, one add and, per width, one subtract and one max.
+// A wave may take a segment of the bins (windows starting in it); segment
+// maxima are combined through LDS.
+// ---------------------------------------------------------------------------
 
-  int r0, n;
-  node_geometry(x.m, t.d_dst, t.node, r0, n);
-  int nrows, s_base;
+template <int... W>
+struct WidthGrid {
+  static constexpr int kN = sizeof...(W);
+  static constexpr int kW[kN] = {W...};
+  static constexpr int kMax = kW[kN - 1];
+};
+using GridPaper9 = WidthGrid<1, 2, 3, 4, 6, 9, 13, 19, 28>;
+using GridDuty9 = WidthGrid<1, 2, 3, 5, 8, 12, 19, 30, 48>;
 
-  if (t.flags & kTileFull) {
-    // load the node's input rows [r0, r0 + n)
-    const int64_t base = x.in_off + (int64_t)r0 * p;
-    for (int it = tid; it < n * nch; it += kThreads) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      float* o = rows + q * stride;
-      const int col0 = c * kChunk;
+__device__ __forceinline__ float nan_max(float a, float b) {
+  return (a != a || b != b) ? __builtin_nanf("") : fmaxf(a, b);
+}
+
+template <class G, bool kCheck>
+__device__ __forceinline__ void ring_block(const float* row, int t, int tend, int p, float& S,
+                                           float (&ring)[G::kMax + 1], float (&best)[G::kN]) {
+  constexpr int NW = G::kN, RS = G::kMax + 1;
+  const float* rp = row + t;
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e) {
-        const int col = col0 + e;
-        if (col < p) {
-          const float v = load_sample(a.in, a.in_dtype, base + (int64_t)q * p + col);
-          o[col] = v;
-          if (col < kChunk - 1) o[p + col] = v;
-        }
-      }
+  for (int u = 0; u < RS; ++u) {
+    float v;
+    if (kCheck) {
+      const int tt = t + u;
+      if (tt >= tend) break;
+      v = row[tt < p ? tt : tt - p];
+    } else {
+      v = rp[u];
     }
-    __syncthreads();
-    // levels from the leaves up; at relative depth lev the block of row q is
-    // found by walking down from the tile's node
-    for (int lev = ceil_log2(n) - 1; lev >= 0; --lev) {
-      for (int q = tid; q < n; q += kThreads) {
-        int b0 = 0, sz = n;
-        for (int k = 0; k < lev; ++k) {
-          const int mh = sz >> 1;
-          if (q - b0 < mh) {
-            sz = mh;
-          } else {
-            b0 += mh;
-            sz -= mh;
-          }
-        }
-        if (sz < 2) {
-          tt[q] = -2;  // a one-row block stays as it is
-        } else {
-          const int s = q - b0, mh = sz >> 1;
-          int i, j;
-          merge_indices(sz, s, i, j);
-          th[q] = b0 + i;
-          tt[q] = b0 + mh + j;
-          tr[q] = (s - j) % p;
-        }
-      }
-      __syncthreads();
-      merge_level(rows, th, tt, tr, n, p, stride, nch, rnch);
-    }
-    nrows = n;
-    s_base = 0;
-  } else {
-    const int L = t.levels;
-    if (tid == 0) build_meta(M, r0, n, t.s0, t.s1, L);
-    __syncthreads();
-    const int lfirst = (1 << L) - 1, llast = (2 << L) - 2;
-    const int total = M.off[llast] + M.hi[llast] - M.lo[llast];
-    // source rows of the bottom level, from the previous pass's scratch
-    for (int q = tid; q < total; q += kThreads) {
-      const int h = find_node(M, L, q);
-      th[q] = M.r0[h] + M.lo[h] + (q - M.off[h]);
-    }
-    __syncthreads();
-    const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
-    for (int it = tid; it < total * nch; it += kThreads) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      const float* g = src + x.scr_off + (int64_t)th[q] * p;
-      float* o = rows + q * stride;
-      const int col0 = c * kChunk;
+    S += v;
+    ring[(u + 1) % RS] = S;
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e) {
-        const int col = col0 + e;
-        if (col < p) {
-          const float v = g[col];
-          o[col] = v;
-          if (col < kChunk - 1) o[p + col] = v;
-        }
-      }
-    }
-    __syncthreads();
-    (void)lfirst;
-    for (int l = L - 1; l >= 0; --l) {
-      const int last = (2 << l) - 2;
-      const int cnt = M.off[last] + M.hi[last] - M.lo[last];
-      for (int q = tid; q < cnt; q += kThreads) {
-        const int h = find_node(M, l, q);
-        const int v = h - ((1 << l) - 1);
-        const int hc = (2 << l) - 1 + 2 * v;
-        const int s = M.lo[h] + (q - M.off[h]);
-        if (M.n[h] >= 2) {
-          int i, j;
-          merge_indices(M.n[h], s, i, j);
-          th[q] = M.off[hc] + (i - M.lo[hc]);
-          tt[q] = M.off[hc + 1] + (j - M.lo[hc + 1]);
-          tr[q] = (s - j) % p;
-        } else {
-          th[q] = M.off[hc + 1];  // one-row block: its tail child's only row
-          tt[q] = -1;
-        }
-      }
-      __syncthreads();
-      merge_level(rows, th, tt, tr, cnt, p, stride, nch, rnch);
-    }
-    nrows = t.s1 - t.s0;
-    s_base = t.s0;
+    for (int k = 0; k < NW; ++k) best[k] = fmaxf(best[k], S - ring[(u + 1 + RS - G::kW[k]) % RS]);
   }
+}
 
-  if (!(t.flags & kTileFinal)) {
-    // intermediate rows of node (r0, n) -> scratch, rows r0 + s_base + q
-    float* dst = (t.bufs & 2) ? a.scr1 : a.scr0;
-    float* g = dst + x.scr_off + (int64_t)(r0 + s_base) * p;
-    for (int it = tid; it < nrows * nch; it += kThreads) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      const float* o = rows + q * stride;
-      const int col0 = c * kChunk;
+template <class G>
+__device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, int nvalid, float* part,
+                         const float* scale, float* out) {
+  constexpr int NW = G::kN, RS = G::kMax + 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ngroups = (nvalid + 63) >> 6;
+  const int nseg = ngroups >= 4 ? 1 : (ngroups > 0 ? 4 / ngroups : 1);
+  const int rpad = ngroups * 64;
+  if (wave < ngroups * nseg) {
+    const int g = wave / nseg, sg = wave - g * nseg;
+    const int q = g * 64 + lane;
+    const int lseg = (p + nseg - 1) / nseg;
+    const int n0 = sg * lseg, n1 = min(p, n0 + lseg);
+    float best[NW];
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e)
-        if (col0 + e < p) g[(int64_t)q * p + col0 + e] = o[col0 + e];
-    }
-    return;
-  }
-  if (t.flags & kTileOutRows) {
-    float* g = a.out_rows + x.out_row0 + (int64_t)s_base * p;
-    for (int it = tid; it < nrows * nch; it += kThreads) {
-      int q, c;
-      split_item(it, nch, rnch, q, c);
-      const float* o = rows + q * stride;
-      const int col0 = c * kChunk;
+    for (int k = 0; k < NW; ++k) best[k] = -INFINITY;
+    float S = 0.0f;
+    if (n0 < n1) {
+      const int tend = n1 + G::kMax - 1;  // windows starting in [n0, n1)
+      const float* row = rows + (q < nvalid ? q : 0) * stride;
+      float ring[RS];
+      ring[0] = 0.0f;
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e)
-        if (col0 + e < p) g[(int64_t)q * p + col0 + e] = o[col0 + e];
+      for (int u = 1; u < RS; ++u) ring[u] = INFINITY;  // before the segment: no window
+      int t = n0;
+      for (; t + RS <= tend && t + RS <= p; t += RS) ring_block<G, false>(row, t, tend, p, S, ring, best);
+      for (; t < tend; t += RS) ring_block<G, true>(row, t, tend, p, S, ring, best);
     }
-    return;
+    if (S != S) {
+#pragma unroll
+      for (int k = 0; k < NW; ++k) best[k] = S;
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) part[(sg * NW + k) * rpad + q] = best[k];
   }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nvalid * NW; idx += kThreads) {
+    const int q = idx / NW, k = idx - q * NW;
+    float v = part[k * rpad + q];
+    for (int sg = 1; sg < nseg; ++sg) v = nan_max(v, part[(sg * NW + k) * rpad + q]);
+    out[idx] = v * scale[k];
+  }
+}
 
-  // Boxcar S/N of the final rows (Sec. 5.4): each wave takes whole rows. The
-  // exclusive prefix S over two repeats of the profile goes to a per-wave LDS
-  // array, S[t] for t <= p + wmax; the boxcar of width w starting at bin n
-  // sums S[n + w] - S[n]; the best over n, times 1 / sqrt(m w var), is the
-  // S/N (the scale is precomputed in FP64).
+// General widths: one wave per row, lane = contiguous phases; the prefix goes
+// to a per-wave LDS array.
+__device__ __forceinline__ void snr_general(const PassArgs& a, const float* rows, int stride, int p, int nvalid,
+                            float* snrbuf, const float* scale, float* out) {
   const int wmax = a.wmax, slen = p + wmax + 1;
   int snr_waves = kSnrLdsBytes / (slen * 4);
   snr_waves = snr_waves < kWaves ? snr_waves : kWaves;
-  const int wave = tid / 64, lane = tid % 64;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   if (wave >= snr_waves) return;
   float* S = snrbuf + wave * slen;
-  const int ncol = (p + 63) / 64;  // contiguous phases per lane for the scan
+  const int ncol = (p + 63) / 64;
   const int nw = a.num_widths;
-  const float* scale = a.scales + x.scale_off;
-  for (int q = wave; q < nrows; q += snr_waves) {
-    const int s = s_base + q;
-    if (s >= x.keep) break;
+  for (int q = wave; q < nvalid; q += snr_waves) {
     const float* row = rows + q * stride;
     float v[kSnrColsMax];
     float run = 0.0f;
@@ -625,8 +665,8 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
       const int col = lane * ncol + e;
       acc += v[e];
       if (e < ncol && col < p) {
-        S[col + 1] = acc;                          // S[col + 1] = sum of bins 0..col
-        if (col < wmax) S[p + 1 + col] = total + acc;  // second repeat
+        S[col + 1] = acc;
+        if (col < wmax) S[p + 1 + col] = total + acc;
       }
     }
     wave_lds_sync();
@@ -638,9 +678,153 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
       best = wave_max(best);
       if (lane == iw) res = best * scale[iw];
     }
-    if (total != total) res = total;  // a NaN anywhere in the profile: NaN S/N (fmaxf drops NaNs)
-    if (lane < nw) a.snr[(x.out_row0 + s) * nw + lane] = res;
+    if (total != total) res = total;  // a NaN anywhere in the profile: NaN S/N
+    if (lane < nw) out[q * nw + lane] = res;
     wave_lds_sync();
+  }
+}
+
+template <int JS, int DT>
+__device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, const XformDesc& x,
+                                         unsigned char* smem) {
+  const int p = x.p, stride = lds_stride(p), J = col_iters(p);
+  const int R = rows_capacity(p, a.lds_rows_cap);
+  float* rows = reinterpret_cast<float*>(smem);
+  const int ZR = R;            // all-zero row
+  float* junk = rows + (R + 1) * stride;
+  int* th = reinterpret_cast<int*>(rows + (R + 2) * stride);
+  int* tt = th + R;
+  int* tr = tt + R;
+  Meta M{tr + R, tr + R + kMetaNodes, tr + R + 2 * kMetaNodes, tr + R + 3 * kMetaNodes,
+         tr + R + 4 * kMetaNodes};
+  float* snrbuf = reinterpret_cast<float*>(tr + R + 5 * kMetaNodes);
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  for (int c = tid; c < stride; c += kThreads) rows[ZR * stride + c] = 0.0f;
+
+  int r0, n;
+  node_geometry(x.m, t.d_dst, t.node, r0, n);
+  int nrows, s_base;
+  const int q_lane = wave + kWaves * lane;  // the wave's row held by this lane
+
+  if (t.flags & kTileFull) {
+    const int64_t base = x.in_off + (int64_t)r0 * p;
+    load_rows<DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
+    if (n >= 2) {
+      const int32_t off = a.full_off[n];
+      // schedule entries of level `lev` for the lane's row, fetched one level
+      // ahead so the loads overlap the previous merge
+      auto fetch = [&](int lev) {
+        LaneOp op{0, ZR, 0};
+        if (lev >= 0 && q_lane < n) {
+          const uint32_t ht = a.full_ht[off + lev * n + q_lane];
+          int rot = a.full_rot[off + lev * n + q_lane];
+          if ((ht >> 16) == 0xffffu) {  // one-row block: stays
+            op.h = q_lane;
+          } else {
+            op.h = (int)(ht & 0xffffu);
+            op.t = (int)(ht >> 16);
+            op.rot = rot >= p ? rot % p : rot;
+          }
+        }
+        return op;
+      };
+      int lev = ceil_log2(n) - 1;
+      LaneOp cur = fetch(lev);
+      __syncthreads();
+      for (; lev >= 0; --lev) {
+        const LaneOp nxt = fetch(lev - 1);
+        merge_level<JS>(rows, n, p, stride, J, cur, junk);
+        cur = nxt;
+      }
+    } else {
+      __syncthreads();
+    }
+    nrows = n;
+    s_base = 0;
+  } else {
+    const int L = t.levels;
+    if (wave == 0) build_meta(M, r0, n, t.s0, t.s1, L);
+    __syncthreads();
+    const int llast = (2 << L) - 2;
+    const int total = M.off[llast] + M.hi[llast] - M.lo[llast];
+    for (int q = tid; q < total; q += kThreads) {
+      const int h = find_node(M, L, q);
+      th[q] = M.r0[h] + M.lo[h] + (q - M.off[h]);
+    }
+    __syncthreads();
+    const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
+    load_rows<FFA_F32>(rows, total, p, stride, src + x.scr_off,
+                       q_lane < total ? (int64_t)th[q_lane] * p : 0);
+    for (int l = L - 1; l >= 0; --l) {
+      const int last = (2 << l) - 2;
+      const int cnt = M.off[last] + M.hi[last] - M.lo[last];
+      __syncthreads();  // rows loaded / previous tables consumed
+      for (int q = tid; q < cnt; q += kThreads) {
+        const int h = find_node(M, l, q);
+        const int v = h - ((1 << l) - 1);
+        const int hc = (2 << l) - 1 + 2 * v;
+        const int s = M.lo[h] + (q - M.off[h]);
+        if (M.n[h] >= 2) {
+          int i, j;
+          merge_indices(M.n[h], s, i, j);
+          th[q] = M.off[hc] + (i - M.lo[hc]);
+          tt[q] = M.off[hc + 1] + (j - M.lo[hc + 1]);
+          tr[q] = (s - j) % p;
+        } else {
+          th[q] = M.off[hc + 1];  // one-row block: its tail child's only row
+          tt[q] = ZR;
+          tr[q] = 0;
+        }
+      }
+      __syncthreads();
+      LaneOp op{0, ZR, 0};
+      if (q_lane < cnt) {
+        op.h = th[q_lane];
+        op.t = tt[q_lane];
+        op.rot = tr[q_lane];
+      }
+      merge_level<JS>(rows, cnt, p, stride, J, op, junk);
+    }
+    nrows = t.s1 - t.s0;
+    s_base = t.s0;
+  }
+
+  if (!(t.flags & kTileFinal)) {
+    float* dst = (t.bufs & 2) ? a.scr1 : a.scr0;
+    store_rows(rows, nrows, p, stride, dst + x.scr_off + (int64_t)(r0 + s_base) * p);
+    return;
+  }
+  if (t.flags & kTileOutRows) {
+    store_rows(rows, nrows, p, stride, a.out_rows + x.out_row0 + (int64_t)s_base * p);
+    return;
+  }
+  int nvalid = x.keep - s_base;
+  nvalid = nvalid < nrows ? nvalid : nrows;
+  if (nvalid <= 0) return;
+  const float* scale = a.scales + x.scale_off;
+  float* out = a.snr + (x.out_row0 + s_base) * a.num_widths;
+  if (a.width_set == kWidthsPaper9)
+    snr_grid<GridPaper9>(rows, stride, p, nvalid, snrbuf, scale, out);
+  else if (a.width_set == kWidthsDuty9)
+    snr_grid<GridDuty9>(rows, stride, p, nvalid, snrbuf, scale, out);
+  else
+    snr_general(a, rows, stride, p, nvalid, snrbuf, scale, out);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const TileDesc t = a.tiles[blockIdx.x];
+  const XformDesc x = a.xf[t.xf];
+  // compile-time variants: one column group per lane (p <= 316) or more, and
+  // the storage type of the input rows of full tiles
+  const bool j1 = col_iters(x.p) == 1;
+  if (a.in_dtype == FFA_BF16) {
+    if (j1) ffa_tile<1, FFA_BF16>(a, t, x, smem); else ffa_tile<0, FFA_BF16>(a, t, x, smem);
+  } else if (a.in_dtype == FFA_F16) {
+    if (j1) ffa_tile<1, FFA_F16>(a, t, x, smem); else ffa_tile<0, FFA_F16>(a, t, x, smem);
+  } else {
+    if (j1) ffa_tile<1, FFA_F32>(a, t, x, smem); else ffa_tile<0, FFA_F32>(a, t, x, smem);
   }
 }
 
@@ -671,9 +855,8 @@ int32_t downsample_block_samples(int32_t max_halo) {
 
 hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
                              const float* norm, int32_t dtype, void* out, int32_t out_dtype,
-                             int64_t nblocks, int32_t block_samples, int32_t max_halo,
-                             hipStream_t stream) {
-  const size_t lds = (size_t)(2 * (block_samples + max_halo) + 2) * sizeof(float);
+                             int64_t nblocks, int32_t lds_floats, hipStream_t stream) {
+  const size_t lds = (size_t)lds_floats * sizeof(float);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample),
@@ -684,7 +867,7 @@ hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const
   }
   if (lds > (size_t)(kLdsBytes - 4096)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_downsample, dim3((unsigned)nblocks), dim3(kDsThreads), lds, stream,
-                     series_dev, nseries, oct, norm, dtype, out, out_dtype, block_samples);
+                     series_dev, nseries, oct, norm, dtype, out, out_dtype);
   return hipGetLastError();
 }
 

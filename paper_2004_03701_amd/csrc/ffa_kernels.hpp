@@ -17,6 +17,8 @@ struct SeriesDev {
   int32_t noct;
   int32_t normalise;
   int32_t halo;       // samples past a block needed by its last window
+  int32_t block;      // samples per downsampling block
+  int32_t pad;
 };
 
 // One pseudo-octave of one series: where its downsampled samples go.
@@ -37,10 +39,11 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
 
 // All pseudo-octaves of every series in one pass over the raw samples
 // (Sec. 5.3, App. A.4). nblocks = total downsampling blocks of the launch.
+// Every series is cut into blocks of its own `block` samples; lds_floats is
+// the largest 2 * (block + halo) + 2 of the launch.
 hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
                              const float* norm, int32_t dtype, void* out, int32_t out_dtype,
-                             int64_t nblocks, int32_t block_samples, int32_t max_halo,
-                             hipStream_t stream);
+                             int64_t nblocks, int32_t lds_floats, hipStream_t stream);
 
 // Downsampling block length for a given largest halo.
 int32_t downsample_block_samples(int32_t max_halo);

@@ -163,6 +163,51 @@ void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n) {
   *n = size;
 }
 
+void build_full_schedules(std::vector<uint32_t>* ht, std::vector<uint16_t>* rot,
+                          std::vector<int32_t>* off) {
+  ht->clear();
+  rot->clear();
+  off->assign(kMaxFullRows + 1, 0);
+  for (int n = 2; n <= kMaxFullRows; ++n) {
+    (*off)[n] = (int32_t)ht->size();
+    int levels = 0;
+    while ((1 << levels) < n) ++levels;
+    for (int lev = 0; lev < levels; ++lev) {
+      for (int q = 0; q < n; ++q) {
+        // block holding row q at relative depth lev
+        int b0 = 0, sz = n;
+        for (int k = 0; k < lev; ++k) {
+          const int mh = sz / 2;
+          if (q - b0 < mh) {
+            sz = mh;
+          } else {
+            b0 += mh;
+            sz -= mh;
+          }
+        }
+        if (sz < 2) {
+          ht->push_back((uint32_t)q | (0xffffu << 16));
+          rot->push_back(0);
+        } else {
+          const int s = q - b0, mh = sz / 2;
+          int64_t i, j;
+          merge_indices(sz, s, &i, &j);
+          ht->push_back((uint32_t)(b0 + i) | ((uint32_t)(b0 + mh + j) << 16));
+          rot->push_back((uint16_t)(s - j));
+        }
+      }
+    }
+  }
+}
+
+int32_t width_set_of(const int32_t* w, int32_t n) {
+  static const int32_t paper[9] = {1, 2, 3, 4, 6, 9, 13, 19, 28};
+  static const int32_t duty[9] = {1, 2, 3, 5, 8, 12, 19, 30, 48};
+  if (n == 9 && std::equal(w, w + 9, paper)) return kWidthsPaper9;
+  if (n == 9 && std::equal(w, w + 9, duty)) return kWidthsDuty9;
+  return kWidthsGeneral;
+}
+
 namespace {
 
 // Rows needed at each of the `levels` levels below a node of n rows to

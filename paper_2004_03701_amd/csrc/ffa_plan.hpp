@@ -63,6 +63,13 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
                           int32_t levels_per_pass, bool out_rows,
                           std::vector<std::vector<TileDesc>>* passes);
 
+// Merge schedules of full subtrees of 2..kMaxFullRows rows (PassArgs).
+void build_full_schedules(std::vector<uint32_t>* ht, std::vector<uint16_t>* rot,
+                          std::vector<int32_t>* off);
+
+// Compiled width grid matching `widths`, or kWidthsGeneral.
+int32_t width_set_of(const int32_t* widths, int32_t n);
+
 // Start row and size of node `node` at depth d of the m-row tree.
 void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n);
 

@@ -173,3 +173,100 @@ def test_invalid_arguments_do_no_device_work(ctx):
     assert e.value.status == ffa.FFA_ERR_BUFFER_TOO_SMALL
     assert "small" in ffa.ffa_last_error(ctx)
     assert (snr == 0).all()
+
+
+def test_search_duty_width_grid(ctx):
+    g = synth.rng(9, 0)
+    x = synth.inject(synth.noise(1 << 21, g),
+                     synth.Pulse(period=1.234 / 64e-6, duty=0.04, amplitude=18.0, phi0=0.7))
+    cfg = synth.config_duty(64e-6, 0.5, 4.0)
+    per, bins, snr = run_search(ctx, x, cfg)
+    ref = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                        cfg.bins_max, cfg.widths)
+    assert np.array_equal(per, ref.periods)
+    assert snr_close(snr, ref.snr) < SNR_RTOL
+    best = np.unravel_index(np.argmax(snr), snr.shape)
+    assert abs(per[best[0]] - 1.234) < 1e-3
+
+
+def test_search_workload2_full(ctx):
+    x, cfg, pulses = synth.workload2()
+    per, bins, snr = run_search(ctx, x, cfg)
+    ref = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                        cfg.bins_max, cfg.widths)
+    assert np.array_equal(per, ref.periods)
+    assert snr_close(snr, ref.snr) < SNR_RTOL
+
+
+def batch_inputs(n):
+    xs, prms = [], []
+    for i in range(n):
+        g = synth.rng(7, i)
+        ns = int(g.integers(300_000, 900_000))
+        x = synth.noise(ns, g)
+        tsamp = [64e-6, 128e-6, 256e-6][i % 3]
+        lo, hi = [(0.1, 1.0), (0.2, 3.0), (1.0, 30.0)][i % 3]
+        xs.append(x)
+        prms.append((tsamp, lo, hi))
+    return xs, prms
+
+
+def test_batch_equals_single_series_bit_for_bit(ctx):
+    xs, cfgs = batch_inputs(7)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
+    snr_b, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    snr_b = snr_b.cpu().numpy()
+    for i in range(len(xs)):
+        _, _, s1 = ffa.ffa_search(ctx, dev_x[i], params[i])
+        torch.cuda.synchronize()
+        s1 = s1.cpu().numpy()
+        assert np.array_equal(snr_b[offs[i]:offs[i] + s1.shape[0]], s1)
+    # spot check one series against the oracle
+    t, lo, hi = cfgs[2]
+    ref = oracle.search(xs[2], t, lo, hi, 240, 259, synth.WIDTHS_DUTY)
+    assert snr_close(snr_b[offs[2]:offs[2] + ref.snr.shape[0]], ref.snr) < SNR_RTOL
+
+
+def test_graph_replay_matches_eager(ctx):
+    xs, cfgs = batch_inputs(4)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
+    eager, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    eager = eager.cpu().numpy()
+    out = torch.full((eager.shape[0], eager.shape[1]), -1.0, device="cuda")
+    for rep in range(4):
+        out.fill_(-1.0)
+        ffa.ffa_search_batch(ctx, dev_x, params, snr=out, row_offset=offs, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        # eager work of the program between replays
+        ffa.ffa_search_batch(ctx, dev_x[:1], params[:1])
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dt,tdt,bound", [(ffa.FFA_BF16, torch.bfloat16, 0.02),
+                                         (ffa.FFA_F16, torch.float16, 2e-3)])
+def test_low_precision_storage(ctx, dt, tdt, bound):
+    g = synth.rng(9, 1)
+    x = synth.noise(1 << 21, g)
+    xq = torch.from_numpy(x).to(tdt)
+    xdq = xq.to(torch.float32).numpy()       # what the kernels actually read
+    cfg = synth.config_duty(64e-6, 0.5, 4.0)
+    prm = ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                          cfg.bins_max, cfg.widths, dtype=dt)
+    _, _, snr = ffa.ffa_search(ctx, xq.cuda(), prm)
+    torch.cuda.synchronize()
+    snr = snr.cpu().numpy()
+    ref = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                        cfg.bins_max, cfg.widths)
+    ref_dq = oracle.search(xdq, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                           cfg.bins_max, cfg.widths)
+    err = np.abs(snr - ref.snr)
+    err_dq = np.abs(snr - ref_dq.snr)
+    print(f"dtype {dt}: vs FP32 input max {err.max():.3e} median {np.median(err):.3e}; "
+          f"vs dequantised input max {err_dq.max():.3e} median {np.median(err_dq):.3e}")
+    assert err.max() < bound * 8 and np.median(err) < bound
+    assert err_dq.max() < bound * 8
