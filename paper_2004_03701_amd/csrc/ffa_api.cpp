@@ -205,6 +205,8 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   for (int i = 0; i < nseries; ++i) {
     const SeriesPlan& pl = *plans[i];
     const ffa_search_params& a = params[i];
+    if (pl.oct.size() > 128)
+      return fail(ctx, FFA_ERR_INVALID_ARG, "more than 128 pseudo-octaves: period range too wide");
     sd[i].ptr = series[i];
     sd[i].nsamp = nsamp[i];
     sd[i].chunk0 = chunk;

@@ -199,6 +199,9 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
   return j;
 }
 
+constexpr int kDsMaxOctaves = 128;
+constexpr int kDsLoadIters = 24;  // samples a thread loads before storing (block + halo <= 24 * 512)
+
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
                                                            int32_t nseries,
                                                            const OctaveDev* oct,
@@ -206,8 +209,11 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
                                                            void* out, int out_dtype) {
   extern __shared__ float sm[];
   __shared__ int s_series;
-  __shared__ float s_part[kDsThreads];
+  __shared__ float s_part[kDsThreads / 64];
+  __shared__ int64_t s_j0[kDsMaxOctaves];
+  __shared__ int s_cum[kDsMaxOctaves + 1];
   const int tid = threadIdx.x;
+  const int lane = tid % 64, wave = tid / 64;
   if (tid == 0) {
     int lo = 0, hi = nseries - 1;  // last series with chunk0 <= blockIdx.x
     while (lo < hi) {
@@ -231,14 +237,53 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   float* ps = sm + len + 1;       // len + 1 prefix sums
   const float mean = sd.normalise ? norm[2 * si] : 0.0f;
   const float inv = sd.normalise ? norm[2 * si + 1] : 1.0f;
-  for (int q = tid; q < len; q += kDsThreads) xs[q] = load_sample(sd.ptr, dtype, c0 + q) - mean;
+  // every load of a thread is in flight before its first LDS store
+  for (int q0 = 0; q0 < len; q0 += kDsLoadIters * kDsThreads) {
+    float v[kDsLoadIters];
+#pragma unroll
+    for (int k = 0; k < kDsLoadIters; ++k) {
+      const int q = q0 + tid + k * kDsThreads;
+      v[k] = q < len ? load_sample(sd.ptr, dtype, c0 + q) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kDsLoadIters; ++k) {
+      const int q = q0 + tid + k * kDsThreads;
+      if (q < len) xs[q] = v[k] - mean;
+    }
+  }
+  // window ranges of every octave, one octave per thread: outputs whose
+  // window starts in [c0, c1) are j in [ceil(c0 / ds), ceil(c1 / ds))
+  const uint64_t lo_fx = (uint64_t)c0 << 32, hi_fx = (uint64_t)c1 << 32;
+  const int noct = min(sd.noct, kDsMaxOctaves);
+  if (tid < noct) {
+    const OctaveDev o = oct[sd.oct0 + tid];
+    int64_t j0 = 0, j1 = 0;
+    if (o.nsamp > 0) {
+      j0 = first_window(lo_fx, o.ds_fx);
+      j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
+    }
+    s_j0[tid] = j0;
+    s_cum[tid + 1] = j1 > j0 ? (int)(j1 - j0) : 0;  // counts, scanned below
+  }
+  __syncthreads();
+  if (wave == 0) {
+    int carry = 0;
+    for (int b = 0; b < noct; b += 64) {
+      const int k = b + lane;
+      const int c = k < noct ? s_cum[k + 1] : 0;
+      const int incl = wave_inclusive_sum(c, lane);
+      wave_lds_sync();
+      if (k < noct) s_cum[k + 1] = carry + incl;
+      carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) s_cum[0] = 0;
+  }
   __syncthreads();
   // exclusive prefix: contiguous segments per thread, then a block scan
   const int seg = (len + kDsThreads - 1) / kDsThreads;
   const int q0 = min(tid * seg, len), q1 = min(q0 + seg, len);
   float run = 0.0f;
   for (int q = q0; q < q1; ++q) run += xs[q];
-  const int lane = tid % 64, wave = tid / 64;
   float incl = wave_inclusive_sum(run, lane);
   if (lane == 63) s_part[wave] = incl;
   __syncthreads();
@@ -252,24 +297,26 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   if (q1 == len && q0 < q1) ps[len] = acc;
   if (len == 0 && tid == 0) ps[0] = 0.0f;
   __syncthreads();
-  const uint64_t lo_fx = (uint64_t)c0 << 32, hi_fx = (uint64_t)c1 << 32;
-  for (int k = 0; k < sd.noct; ++k) {
-    const OctaveDev o = oct[sd.oct0 + k];
-    if (o.nsamp == 0) continue;
-    // outputs whose window starts in [c0, c1): j in [ceil(c0 / ds), ceil(c1 / ds))
-    const int64_t j0 = first_window(lo_fx, o.ds_fx);
-    const int64_t j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
-    const int nj = (int)(j1 - j0);
-    for (int r = tid; r < nj; r += kDsThreads) {
-      const int64_t j = j0 + r;
-      const uint64_t a = (uint64_t)j * o.ds_fx, b = a + o.ds_fx;
-      const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
-      const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
-      const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
-      float y = (1.0f - fa) * xs[ia] + (ps[ib] - ps[ia + 1]);
-      if ((uint32_t)b != 0u) y += fb * xs[ib];
-      store_sample(out, out_dtype, o.off + j, y * inv);
+  // all outputs of all octaves, flattened
+  const int total = s_cum[noct];
+  for (int u = tid; u < total; u += kDsThreads) {
+    int lo = 0, hi = noct - 1;  // octave k with s_cum[k] <= u < s_cum[k + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (s_cum[mid] <= u)
+        lo = mid;
+      else
+        hi = mid - 1;
     }
+    const OctaveDev o = oct[sd.oct0 + lo];
+    const int64_t j = s_j0[lo] + (u - s_cum[lo]);
+    const uint64_t a = (uint64_t)j * o.ds_fx, b = a + o.ds_fx;
+    const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
+    const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
+    const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
+    float y = (1.0f - fa) * xs[ia] + (ps[ib] - ps[ia + 1]);
+    if ((uint32_t)b != 0u) y += fb * xs[ib];
+    store_sample(out, out_dtype, o.off + j, y * inv);
   }
 }
 
@@ -407,8 +454,11 @@ __device__ __forceinline__ void merge_level(float* rows, int count, int p, int s
 
 // Loads rows [0, count) into LDS with their wrapped copies; lane r of each
 // wave holds in `src` the element offset of the wave's row r. Lanes take
-// consecutive columns (coalesced), four rows at a time.
-template <int DT>
+// consecutive columns (coalesced). With one column group per lane (JS = 1,
+// rows of at most 316 bins) every load of a lane is issued before its first
+// LDS store, so a tile pays one memory round trip; wider rows go four rows at
+// a time.
+template <int JS, int DT>
 __device__ __forceinline__ void load_rows(float* rows, int count, int p, int stride,
                                           const void* base, int64_t src) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -416,6 +466,30 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
   const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
   const int width = p + kChunk - 1;
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
+  if (JS == 1) {
+    constexpr int KC = 5;  // 5 x 64 columns >= p + kChunk - 1 for p <= 316
+    float v[kStageMax][KC];
+#pragma unroll
+    for (int r = 0; r < kStageMax; ++r) {
+      const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
+                        ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int c = lane + 64 * k;
+        int col = c < p ? c : c - p;
+        if (col >= p) col %= p;  // rows shorter than the copy
+        v[r][k] = (r < nrw && c < width) ? load_sample(base, DT, g + col) : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kStageMax; ++r)
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int c = lane + 64 * k;
+        if (r < nrw && c < width) rows[(wave + kWaves * r) * stride + c] = v[r][k];
+      }
+    return;
+  }
   for (int rb = 0; rb < nrw; rb += 4) {
     int64_t g[4];
 #pragma unroll
@@ -430,7 +504,7 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
           int col = c < p ? c : c - p;
-          if (col >= p) col %= p;  // rows shorter than the copy
+          if (col >= p) col %= p;
           v[u][k] = (rb + u < nrw && c < width) ? load_sample(base, DT, g[u] + col) : 0.0f;
         }
 #pragma unroll
@@ -445,11 +519,31 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
 }
 
 // Writes rows [0, count) of LDS to global rows dst + q * p, coalesced.
+template <int JS>
 __device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
                                            float* dst) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  if (JS == 1) {
+    constexpr int KC = 5;
+    float v[kStageMax][KC];
+#pragma unroll
+    for (int r = 0; r < kStageMax; ++r)
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int c = lane + 64 * k;
+        v[r][k] = (r < nrw && c < p) ? rows[(wave + kWaves * r) * stride + c] : 0.0f;
+      }
+#pragma unroll
+    for (int r = 0; r < kStageMax; ++r)
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int c = lane + 64 * k;
+        if (r < nrw && c < p) dst[(int64_t)(wave + kWaves * r) * p + c] = v[r][k];
+      }
+    return;
+  }
   for (int rb = 0; rb < nrw; rb += 4) {
     for (int c0 = 0; c0 < p; c0 += 128) {
       float v[4][2];
@@ -709,7 +803,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
 
   if (t.flags & kTileFull) {
     const int64_t base = x.in_off + (int64_t)r0 * p;
-    load_rows<DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
+    load_rows<JS, DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
     if (n >= 2) {
       const int32_t off = a.full_off[n];
       // schedule entries of level `lev` for the lane's row, fetched one level
@@ -754,7 +848,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     }
     __syncthreads();
     const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
-    load_rows<FFA_F32>(rows, total, p, stride, src + x.scr_off,
+    load_rows<JS, FFA_F32>(rows, total, p, stride, src + x.scr_off,
                        q_lane < total ? (int64_t)th[q_lane] * p : 0);
     for (int l = L - 1; l >= 0; --l) {
       const int last = (2 << l) - 2;
@@ -792,11 +886,11 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
 
   if (!(t.flags & kTileFinal)) {
     float* dst = (t.bufs & 2) ? a.scr1 : a.scr0;
-    store_rows(rows, nrows, p, stride, dst + x.scr_off + (int64_t)(r0 + s_base) * p);
+    store_rows<JS>(rows, nrows, p, stride, dst + x.scr_off + (int64_t)(r0 + s_base) * p);
     return;
   }
   if (t.flags & kTileOutRows) {
-    store_rows(rows, nrows, p, stride, a.out_rows + x.out_row0 + (int64_t)s_base * p);
+    store_rows<JS>(rows, nrows, p, stride, a.out_rows + x.out_row0 + (int64_t)s_base * p);
     return;
   }
   int nvalid = x.keep - s_base;
@@ -812,20 +906,14 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     snr_general(a, rows, stride, p, nvalid, snrbuf, scale, out);
 }
 
+// One instantiation per (column groups per lane, input storage type): JS = 1
+// needs every tile's p <= 316 (one group per lane); JS = 0 serves any p.
+template <int JS, int DT>
 __global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc t = a.tiles[blockIdx.x];
   const XformDesc x = a.xf[t.xf];
-  // compile-time variants: one column group per lane (p <= 316) or more, and
-  // the storage type of the input rows of full tiles
-  const bool j1 = col_iters(x.p) == 1;
-  if (a.in_dtype == FFA_BF16) {
-    if (j1) ffa_tile<1, FFA_BF16>(a, t, x, smem); else ffa_tile<0, FFA_BF16>(a, t, x, smem);
-  } else if (a.in_dtype == FFA_F16) {
-    if (j1) ffa_tile<1, FFA_F16>(a, t, x, smem); else ffa_tile<0, FFA_F16>(a, t, x, smem);
-  } else {
-    if (j1) ffa_tile<1, FFA_F32>(a, t, x, smem); else ffa_tile<0, FFA_F32>(a, t, x, smem);
-  }
+  ffa_tile<JS, DT>(a, t, x, smem);
 }
 
 }  // namespace
@@ -877,17 +965,31 @@ int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
   return kLdsBytes;
 }
 
-hipError_t launch_pass(const PassArgs& args, hipStream_t stream) {
+template <int JS, int DT>
+hipError_t launch_pass_t(const PassArgs& args, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_pass),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_pass<JS, DT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  if (args.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ffa_pass, dim3(args.ntiles), dim3(kThreads), kLdsBytes, stream, args);
+  hipLaunchKernelGGL((k_ffa_pass<JS, DT>), dim3(args.ntiles), dim3(kThreads), kLdsBytes, stream,
+                     args);
   return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassArgs& args, hipStream_t stream) {
+  if (args.ntiles <= 0) return hipSuccess;
+  const bool j1 = col_iters(args.max_p) == 1;
+  switch (args.in_dtype) {
+    case FFA_BF16:
+      return j1 ? launch_pass_t<1, FFA_BF16>(args, stream) : launch_pass_t<0, FFA_BF16>(args, stream);
+    case FFA_F16:
+      return j1 ? launch_pass_t<1, FFA_F16>(args, stream) : launch_pass_t<0, FFA_F16>(args, stream);
+    default:
+      return j1 ? launch_pass_t<1, FFA_F32>(args, stream) : launch_pass_t<0, FFA_F32>(args, stream);
+  }
 }
 
 hipError_t launch_norm_from_stats(const double* stats, float* norm, hipStream_t stream) {
