@@ -162,12 +162,16 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
  * since the previous call to ffa_sync_status had zero or non-finite variance. */
 ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);
 
-/* Tile shapes used by the search kernels. lds_rows: rows of a profile tile
- * held in LDS (0 = the largest that fits); levels_per_pass: merge levels per
- * pass above the bottom subtrees (1..4). */
+/* Tile shapes and scheduling of the search kernels. lds_rows: rows of a
+ * profile tile held in LDS (0 = the largest that fits); levels_per_pass:
+ * merge levels per pass above the bottom subtrees (1..4); persistent: 1 runs
+ * all passes of a group of series in one persistent launch (tiles taken in
+ * ticket order, later passes waiting on per-transform completion counters),
+ * 0 launches one kernel per pass. */
 typedef struct {
   int32_t lds_rows;
   int32_t levels_per_pass;
+  int32_t persistent;
 } ffa_tiling;
 
 /* Reads or sets the context's tiling. */

@@ -77,7 +77,10 @@ struct Launch {
   int32_t ntiles;
 };
 struct Group {
-  std::vector<Launch> passes;
+  std::vector<Launch> passes;  // one launch per pass, or
+  Launch persist{0, 0};        // all passes in one persistent launch
+  int32_t ncounters = 0;
+  size_t need_off = 0;
 };
 struct Job {
   int32_t nseries = 0;
@@ -95,7 +98,9 @@ struct Job {
   int64_t cells = 0;        // sum of m * p
   int64_t input_samples = 0;
   std::vector<Group> groups;
-  DevBuf series, oct, xf, scales, tiles;
+  bool persistent = false;
+  int32_t max_counters = 0;
+  DevBuf series, oct, xf, scales, tiles, need;
   int32_t stats_blocks = 0;
 };
 
@@ -127,6 +132,8 @@ struct ffa_ctx {
   std::map<std::string, std::shared_ptr<GraphEntry>> graphs;
   DevBuf ds_buf, scr0, scr1, stats, norm, partials, flag, tune_out;
   DevBuf full_ht, full_rot, full_off;  // merge schedules of full subtrees
+  DevBuf counters, ticket;              // persistent scheduler state
+  int num_cus = 256;
   size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
 };
 
@@ -252,19 +259,65 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   job->ds_total = ds_off;
   job->ds_blocks = chunk;
   std::vector<TileDesc> tiles;
+  std::vector<int32_t> need;
   job->scr_cells = 0;
+  job->persistent = ctx->tiling.persistent != 0;
   for (const GroupSpan& g : spans) {
-    std::vector<std::vector<TileDesc>> passes;
-    for (size_t k = g.xf0; k < g.xf1; ++k) {
-      const XformDesc& x = xf[k];
-      plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
-                           rows_capacity(x.p, ctx->tiling.lds_rows),
-                           ctx->tiling.levels_per_pass, false, &passes);
-    }
     Group grp;
-    for (auto& ps : passes) {
-      grp.passes.push_back(Launch{tiles.size(), (int32_t)ps.size()});
-      tiles.insert(tiles.end(), ps.begin(), ps.end());
+    if (!job->persistent) {
+      std::vector<std::vector<TileDesc>> passes;
+      for (size_t k = g.xf0; k < g.xf1; ++k) {
+        const XformDesc& x = xf[k];
+        plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
+                             rows_capacity(x.p, ctx->tiling.lds_rows),
+                             ctx->tiling.levels_per_pass, false, &passes);
+      }
+      for (auto& ps : passes) {
+        grp.passes.push_back(Launch{tiles.size(), (int32_t)ps.size()});
+        tiles.insert(tiles.end(), ps.begin(), ps.end());
+      }
+    } else {
+      // Ticket order: pass k of the transforms of chunk c runs in slot c + k,
+      // so a transform's later passes follow its first pass closely (its
+      // intermediate rows are still in the caches) and never wait long.
+      constexpr int kChunkXf = 32;
+      struct Keyed {
+        int64_t slot, pass, xf, idx;
+        TileDesc t;
+      };
+      std::vector<Keyed> all;
+      grp.need_off = need.size();
+      for (size_t k = g.xf0; k < g.xf1; ++k) {
+        const XformDesc& x = xf[k];
+        std::vector<std::vector<TileDesc>> passes;
+        plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
+                             rows_capacity(x.p, ctx->tiling.lds_rows),
+                             ctx->tiling.levels_per_pass, false, &passes);
+        const int64_t local = (int64_t)(k - g.xf0);
+        const int32_t cbase = (int32_t)(local * kMaxPasses);
+        for (int pk = 0; pk < kMaxPasses; ++pk)
+          need.push_back(pk < (int)passes.size() ? (int32_t)passes[pk].size() : 0);
+        if ((int)passes.size() > kMaxPasses)
+          return fail(ctx, FFA_ERR_INVALID_ARG, "transform needs too many passes");
+        for (int pk = 0; pk < (int)passes.size(); ++pk) {
+          for (size_t ti = 0; ti < passes[pk].size(); ++ti) {
+            TileDesc t = passes[pk][ti];
+            t.dep = pk > 0 ? cbase + pk - 1 : -1;
+            t.done = pk + 1 < (int)passes.size() ? cbase + pk : -1;
+            all.push_back(Keyed{local / kChunkXf + pk, pk, local, (int64_t)ti, t});
+          }
+        }
+      }
+      std::stable_sort(all.begin(), all.end(), [](const Keyed& a, const Keyed& b) {
+        if (a.slot != b.slot) return a.slot < b.slot;
+        if (a.pass != b.pass) return a.pass < b.pass;
+        if (a.xf != b.xf) return a.xf < b.xf;
+        return a.idx < b.idx;
+      });
+      grp.persist = Launch{tiles.size(), (int32_t)all.size()};
+      for (const Keyed& kt : all) tiles.push_back(kt.t);
+      grp.ncounters = (int32_t)((g.xf1 - g.xf0) * kMaxPasses);
+      job->max_counters = std::max(job->max_counters, grp.ncounters);
     }
     job->groups.push_back(grp);
     job->scr_cells = std::max(job->scr_cells, g.cells);
@@ -279,6 +332,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
   HIP_TRY(ctx, upload(job->scales, scales), "upload scale table");
   HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
+  HIP_TRY(ctx, upload(job->need, need), "upload dependency table");
   return FFA_OK;
 }
 
@@ -286,16 +340,18 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
 // addresses, so they are dropped whenever a buffer moves.
 ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
   const size_t db = dtype_bytes(job.dtype);
-  DevBuf* bufs[] = {&ctx->ds_buf, &ctx->scr0, &ctx->scr1, &ctx->stats,
-                    &ctx->norm,   &ctx->partials, &ctx->flag};
+  DevBuf* bufs[] = {&ctx->ds_buf, &ctx->scr0, &ctx->scr1, &ctx->stats, &ctx->norm,
+                    &ctx->partials, &ctx->flag, &ctx->counters, &ctx->ticket};
   const size_t want[] = {(size_t)job.ds_total * db + 16,
                          (size_t)job.scr_cells * 4 + 16,
                          (size_t)job.scr_cells * 4 + 16,
                          (size_t)job.nseries * 2 * sizeof(double),
                          (size_t)job.nseries * 2 * sizeof(float),
                          (size_t)job.nseries * job.stats_blocks * 2 * sizeof(double),
+                         16,
+                         (size_t)std::max(job.max_counters, 1) * sizeof(int32_t),
                          16};
-  for (int b = 0; b < 7; ++b) {
+  for (int b = 0; b < 9; ++b) {
     void* before = bufs[b]->ptr;
     HIP_TRY(ctx, bufs[b]->reserve(want[b]), "allocate workspace");
     if (before && bufs[b]->ptr != before) ctx->graphs.clear();
@@ -377,8 +433,20 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   pa.max_p = job.max_p;
   pa.width_set = width_set_of(job.widths, job.num_widths);
   set_schedules(ctx, &pa);
+  pa.ticket = ctx->ticket.as<int32_t>();
+  pa.counters = ctx->counters.as<int32_t>();
+  pa.error_flag = ctx->flag.as<int32_t>();
+  pa.spin_limit = 1 << 22;
   const TileDesc* tiles = job.tiles.as<TileDesc>();
   for (const Group& g : job.groups) {
+    if (job.persistent) {
+      pa.tiles = tiles + g.persist.tile_off;
+      pa.ntiles = g.persist.ntiles;
+      pa.need = job.need.as<int32_t>() + g.need_off;
+      TimedScope ts(ctx, 2, stream, timed);
+      HIP_TRY(ctx, launch_persist(pa, g.ncounters, ctx->num_cus, stream), "persistent fold kernel");
+      continue;
+    }
     for (const Launch& l : g.passes) {
       pa.tiles = tiles + l.tile_off;
       pa.ntiles = l.ntiles;
@@ -393,7 +461,8 @@ std::string job_key(int32_t nseries, const void* const* series, const int64_t* n
                     const ffa_search_params* params, const int64_t* row_offset,
                     const Tiling& tiling) {
   std::ostringstream k;
-  k << nseries << '|' << tiling.lds_rows << ',' << tiling.levels_per_pass << '|';
+  k << nseries << '|' << tiling.lds_rows << ',' << tiling.levels_per_pass << ','
+    << tiling.persistent << '|';
   for (int i = 0; i < nseries; ++i)
     k << series[i] << ',' << row_offset[i] << ',' << params[i].normalise << ','
       << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
@@ -493,6 +562,9 @@ ffa_status ffa_create(int device, ffa_ctx** out) {
   ffa_ctx* c = new (std::nothrow) ffa_ctx();
   if (!c) return FFA_ERR_NOMEM;
   c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
   std::vector<uint32_t> ht;
   std::vector<uint16_t> rot;
   std::vector<int32_t> off;
@@ -725,6 +797,7 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream) {
   HIP_TRY(ctx, hipMemcpy(&f, ctx->flag.ptr, sizeof f, hipMemcpyDeviceToHost), "read flag");
   HIP_TRY(ctx, launch_clear_flag(ctx->flag.as<int32_t>(), st), "clear flag");
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
+  if (f & 2) return fail(ctx, FFA_ERR_DEVICE, "a fold dependency wait timed out");
   if (f) return fail(ctx, FFA_ERR_DEGENERATE, "a normalised series had zero or non-finite variance");
   return FFA_OK;
 }
@@ -733,16 +806,19 @@ ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out) {
   if (!ctx || !out) return FFA_ERR_INVALID_ARG;
   out->lds_rows = ctx->tiling.lds_rows;
   out->levels_per_pass = ctx->tiling.levels_per_pass;
+  out->persistent = ctx->tiling.persistent;
   return FFA_OK;
 }
 
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* t) {
   if (!ctx || !t) return FFA_ERR_INVALID_ARG;
   if (t->lds_rows < 0 || (t->lds_rows > 0 && t->lds_rows < 16) || t->levels_per_pass < 1 ||
-      t->levels_per_pass > kMaxRangeLevels)
-    return fail(ctx, FFA_ERR_INVALID_ARG, "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4");
+      t->levels_per_pass > kMaxRangeLevels || (t->persistent != 0 && t->persistent != 1))
+    return fail(ctx, FFA_ERR_INVALID_ARG,
+                "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4, persistent 0 or 1");
   ctx->tiling.lds_rows = t->lds_rows;
   ctx->tiling.levels_per_pass = t->levels_per_pass;
+  ctx->tiling.persistent = t->persistent;
   return FFA_OK;
 }
 

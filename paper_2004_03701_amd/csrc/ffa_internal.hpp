@@ -85,6 +85,10 @@ struct TileDesc {
   uint8_t levels;    // range tiles: merge levels in this pass
   uint8_t flags;
   uint8_t bufs;      // bit 0: scratch buffer read, bit 1: scratch buffer written
+  // Persistent launches: the tile starts once counter `dep` reaches need[dep]
+  // (-1: no wait) and adds one to counter `done` when finished (-1: none).
+  int32_t dep;
+  int32_t done;
 };
 
 // Arguments of one pass launch.
@@ -112,7 +116,17 @@ struct PassArgs {
   const uint32_t* full_ht;
   const uint16_t* full_rot;
   const int32_t* full_off;
+  // Persistent launches: tile tickets, per-pass completion counters, and the
+  // error word (bit 1: a dependency wait gave up after spin_limit polls).
+  int32_t* ticket;
+  int32_t* counters;
+  const int32_t* need;
+  int32_t* error_flag;
+  int32_t spin_limit;
 };
+
+// Passes of one transform tracked by the persistent scheduler.
+constexpr int kMaxPasses = 8;
 
 // Width grids the S/N step is compiled for (registers instead of LDS for the
 // prefix history).

@@ -916,6 +916,61 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
   ffa_tile<JS, DT>(a, t, x, smem);
 }
 
+// Persistent form: one workgroup per CU takes tiles in ticket order. A tile of
+// a later pass first waits (one thread, bounded polling) until every tile of
+// the pass it reads has finished; the tiles it waits for carry smaller
+// tickets, so they are held by running workgroups and the wait always ends.
+// Finished tiles publish their rows with an agent-scope release before they
+// count themselves done.
+template <int JS, int DT>
+__global__ __launch_bounds__(kThreads) void k_ffa_persist(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  // the tile layout leaves the last 64 bytes of the LDS unused (rows_capacity)
+  int* s_ticket = reinterpret_cast<int*>(smem + kLdsBytes - 16);
+  // the next ticket is fetched while the current tile is processed
+  int next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(a.ticket, 1);
+  for (;;) {
+    if (threadIdx.x == 0) *s_ticket = next;
+    __syncthreads();
+    const int tk = *s_ticket;
+    __syncthreads();
+    if (tk >= a.ntiles) break;
+    if (threadIdx.x == 0) next = atomicAdd(a.ticket, 1);
+    const TileDesc t = a.tiles[tk];
+    if (t.dep >= 0) {
+      if (threadIdx.x == 0) {
+        const int need = a.need[t.dep];
+        int spins = 0;
+        while (__hip_atomic_load(a.counters + t.dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               need) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins > a.spin_limit ||
+              (__hip_atomic_load(a.error_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
+            atomicOr(a.error_flag, 2);  // give up: later waits end at once
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // later reads see the rows
+      }
+      __syncthreads();
+    }
+    const XformDesc x = a.xf[t.xf];
+    ffa_tile<JS, DT>(a, t, x, smem);
+    __syncthreads();
+    if (threadIdx.x == 0 && t.done >= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(a.counters + t.done, 1);
+    }
+  }
+}
+
+__global__ void k_zero_ints(int32_t* p, int n, int32_t* ticket) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+  if (i == 0) *ticket = 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -963,6 +1018,39 @@ int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
   (void)rows_cap;
   (void)max_p;
   return kLdsBytes;
+}
+
+template <int JS, int DT>
+hipError_t launch_persist_t(const PassArgs& args, int grid, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_persist<JS, DT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_ffa_persist<JS, DT>), dim3(grid), dim3(kThreads), kLdsBytes, stream, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_persist(const PassArgs& args, int ncounters, int grid, hipStream_t stream) {
+  if (args.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ints, dim3((ncounters + 255) / 256), dim3(256), 0, stream,
+                     args.counters, ncounters, args.ticket);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool j1 = col_iters(args.max_p) == 1;
+  switch (args.in_dtype) {
+    case FFA_BF16:
+      return j1 ? launch_persist_t<1, FFA_BF16>(args, grid, stream)
+                : launch_persist_t<0, FFA_BF16>(args, grid, stream);
+    case FFA_F16:
+      return j1 ? launch_persist_t<1, FFA_F16>(args, grid, stream)
+                : launch_persist_t<0, FFA_F16>(args, grid, stream);
+    default:
+      return j1 ? launch_persist_t<1, FFA_F32>(args, grid, stream)
+                : launch_persist_t<0, FFA_F32>(args, grid, stream);
+  }
 }
 
 template <int JS, int DT>

@@ -52,6 +52,10 @@ int32_t downsample_block_samples(int32_t max_halo);
 // final rows (Sec. 5.4).
 hipError_t launch_pass(const PassArgs& args, hipStream_t stream);
 
+// All passes of a group of transforms in one persistent launch of `grid`
+// workgroups; zeroes the ncounters completion counters and the ticket first.
+hipError_t launch_persist(const PassArgs& args, int ncounters, int grid, hipStream_t stream);
+
 // LDS bytes a pass launch uses.
 int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p);
 

@@ -246,7 +246,7 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
   };
   const uint8_t fin = kTileFinal | (out_rows ? kTileOutRows : 0);
   if (m <= rows_cap) {
-    TileDesc t{xf, 0, 0, m, 0, 0, (uint8_t)(kTileFull | fin), 0};
+    TileDesc t{xf, 0, 0, m, 0, 0, (uint8_t)(kTileFull | fin), 0, -1, -1};
     pass(0).push_back(t);
     return;
   }
@@ -256,7 +256,8 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
   for (int64_t nd = 0; nd < (int64_t(1) << db); ++nd) {
     int64_t r0, n;
     node_geometry(m, db, nd, &r0, &n);
-    TileDesc t{xf, (int32_t)nd, 0, (int32_t)n, (uint8_t)db, 0, kTileFull, 0 /* writes buffer 0 */};
+    TileDesc t{xf, (int32_t)nd, 0, (int32_t)n, (uint8_t)db, 0, kTileFull, 0 /* writes buffer 0 */,
+               -1, -1};
     pass(0).push_back(t);
   }
   const int L = std::max(1, std::min<int>(levels_per_pass, kMaxRangeLevels));
@@ -283,7 +284,7 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
             hi = mid - 1;
         }
         TileDesc t{xf, (int32_t)nd, (int32_t)s0, (int32_t)lo, (uint8_t)d_dst, (uint8_t)lv,
-                   (uint8_t)(last ? fin : 0), (uint8_t)(rd | (wr << 1))};
+                   (uint8_t)(last ? fin : 0), (uint8_t)(rd | (wr << 1)), -1, -1};
         pass(k + 1).push_back(t);
         s0 = lo;
       }

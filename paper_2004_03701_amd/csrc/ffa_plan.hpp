@@ -52,6 +52,7 @@ double trial_period(int64_t s, int64_t m, int64_t p, double tau);
 struct Tiling {
   int32_t lds_rows = 0;         // 0: the largest that fits
   int32_t levels_per_pass = 4;  // 1..kMaxRangeLevels
+  int32_t persistent = 1;       // 1: one persistent launch per group of series
 };
 
 // Rows of a p-bin profile tile that fit in one workgroup's LDS.

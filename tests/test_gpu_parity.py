@@ -270,3 +270,38 @@ def test_low_precision_storage(ctx, dt, tdt, bound):
           f"vs dequantised input max {err_dq.max():.3e} median {np.median(err_dq):.3e}")
     assert err.max() < bound * 8 and np.median(err) < bound
     assert err_dq.max() < bound * 8
+
+
+def test_persistent_launch_equals_pass_launches(ctx):
+    # same tiles either way: the periodograms are bit-identical
+    xs, cfgs = batch_inputs(5)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
+    ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
+    a, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    ffa.ffa_set_tiling(ctx, 0, 4, persistent=False)
+    try:
+        b, _ = ffa.ffa_search_batch(ctx, dev_x, params)
+        torch.cuda.synchronize()
+    finally:
+        ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("lds_rows,levels,persistent", [(32, 2, True), (64, 3, False),
+                                                        (48, 1, True), (0, 2, True)])
+def test_search_tilings_agree(ctx, lds_rows, levels, persistent):
+    # the FFA addition tree does not depend on the tiling; the boxcar prefix
+    # sums start at the segment a wave takes, so S/N agrees to FP32 rounding
+    x = synth.noise(1 << 21, synth.rng(9, 2))
+    cfg = synth.config_duty(64e-6, 0.5, 4.0)
+    ref = run_search(ctx, x, cfg)[2]
+    ffa.ffa_set_tiling(ctx, lds_rows, levels, persistent=persistent)
+    try:
+        got = run_search(ctx, x, cfg)[2]
+    finally:
+        ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    assert snr_close(got, ref.astype(np.float64)) < 2e-6
