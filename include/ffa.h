@@ -167,21 +167,27 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);
  * merge levels per pass above the bottom subtrees (1..4); persistent: 1 runs
  * all passes of a group of series in one persistent launch (tiles taken in
  * ticket order, later passes waiting on per-transform completion counters),
- * 0 launches one kernel per pass. */
+ * 0 launches one kernel per pass; waves_per_group: 16 (one workgroup per CU
+ * with all 160 KiB of LDS) or 8 (two workgroups per CU, 80 KiB each). */
 typedef struct {
   int32_t lds_rows;
   int32_t levels_per_pass;
   int32_t persistent;
+  int32_t waves_per_group;
 } ffa_tiling;
 
 /* Reads or sets the context's tiling. */
 ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out);
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* tiling);
 
-/* Times every candidate tiling on a representative batch (same arguments as
- * ffa_search_batch, outputs to a context-owned buffer), keeps the fastest in
- * the context and, if cache_path is not NULL, appends it to that text file
- * keyed by the batch's shape. *best receives the chosen tiling (may be NULL). */
+/* Times candidate tilings (8 or 16 waves per workgroup, 2, 3 or 4 levels per
+ * pass, per-pass or persistent launches) on a representative batch (same
+ * arguments as ffa_search_batch; outputs go to a context-owned buffer) with
+ * HIP events on `stream`, keeps the fastest in the context and, if cache_path
+ * is not NULL, appends it to that text file keyed by a hash of the batch's
+ * shape; a later call with the same shape and file reads the choice back
+ * without timing. *best receives the chosen tiling (may be NULL). The call
+ * synchronises the stream. */
 ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                         const int64_t* nsamp, const ffa_search_params* params,
                         const char* cache_path, ffa_tiling* best, void* stream);

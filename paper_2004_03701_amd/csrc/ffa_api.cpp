@@ -99,6 +99,7 @@ struct Job {
   int64_t input_samples = 0;
   std::vector<Group> groups;
   bool persistent = false;
+  Tiling tiling;            // tiling the tables were built for
   int32_t max_counters = 0;
   DevBuf series, oct, xf, scales, tiles, need;
   int32_t stats_blocks = 0;
@@ -191,6 +192,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                      const int64_t* row_offset, const std::vector<std::shared_ptr<SeriesPlan>>& plans,
                      Job* job) {
   job->nseries = nseries;
+  job->tiling = ctx->tiling;
   job->dtype = params[0].dtype;
   job->num_widths = params[0].num_widths;
   for (int q = 0; q < job->num_widths; ++q) job->widths[q] = params[0].widths[q];
@@ -269,7 +271,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
         plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
-                             rows_capacity(x.p, ctx->tiling.lds_rows),
+                             rows_capacity(x.p, ctx->tiling),
                              ctx->tiling.levels_per_pass, false, &passes);
       }
       for (auto& ps : passes) {
@@ -291,7 +293,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
         const XformDesc& x = xf[k];
         std::vector<std::vector<TileDesc>> passes;
         plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
-                             rows_capacity(x.p, ctx->tiling.lds_rows),
+                             rows_capacity(x.p, ctx->tiling),
                              ctx->tiling.levels_per_pass, false, &passes);
         const int64_t local = (int64_t)(k - g.xf0);
         const int32_t cbase = (int32_t)(local * kMaxPasses);
@@ -418,7 +420,8 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
           "downsample kernel");
   }
   PassArgs pa{};
-  pa.lds_rows_cap = ctx->tiling.lds_rows;
+  pa.lds_rows_cap = job.tiling.lds_rows;
+  pa.waves = job.tiling.waves;
   pa.xf = job.xf.as<XformDesc>();
   pa.in = ctx->ds_buf.ptr;
   pa.in_dtype = job.dtype;
@@ -444,7 +447,9 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
       pa.ntiles = g.persist.ntiles;
       pa.need = job.need.as<int32_t>() + g.need_off;
       TimedScope ts(ctx, 2, stream, timed);
-      HIP_TRY(ctx, launch_persist(pa, g.ncounters, ctx->num_cus, stream), "persistent fold kernel");
+      HIP_TRY(ctx, launch_persist(pa, g.ncounters, ctx->num_cus * (kWavesLarge / job.tiling.waves),
+                                  stream),
+              "persistent fold kernel");
       continue;
     }
     for (const Launch& l : g.passes) {
@@ -462,7 +467,7 @@ std::string job_key(int32_t nseries, const void* const* series, const int64_t* n
                     const Tiling& tiling) {
   std::ostringstream k;
   k << nseries << '|' << tiling.lds_rows << ',' << tiling.levels_per_pass << ','
-    << tiling.persistent << '|';
+    << tiling.persistent << ',' << tiling.waves << '|';
   for (int i = 0; i < nseries; ++i)
     k << series[i] << ',' << row_offset[i] << ',' << params[i].normalise << ','
       << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
@@ -693,7 +698,7 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
     HIP_TRY(ctx, hipMemcpyAsync(out, in, (size_t)p * 4, hipMemcpyDeviceToDevice, st), "copy");
     return FFA_OK;
   }
-  plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling.lds_rows),
+  plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling),
                        ctx->tiling.levels_per_pass, true, &passes);
   std::vector<TileDesc> tiles;
   std::vector<Launch> launches;
@@ -709,6 +714,7 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   HIP_TRY(ctx, ctx->scr1.reserve((size_t)m * p * 4 + 16), "allocate scratch");
   PassArgs pa{};
   pa.lds_rows_cap = ctx->tiling.lds_rows;
+  pa.waves = ctx->tiling.waves;
   pa.xf = job->xf.as<XformDesc>();
   pa.in = in;
   pa.in_dtype = FFA_F32;
@@ -807,18 +813,22 @@ ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out) {
   out->lds_rows = ctx->tiling.lds_rows;
   out->levels_per_pass = ctx->tiling.levels_per_pass;
   out->persistent = ctx->tiling.persistent;
+  out->waves_per_group = ctx->tiling.waves;
   return FFA_OK;
 }
 
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* t) {
   if (!ctx || !t) return FFA_ERR_INVALID_ARG;
   if (t->lds_rows < 0 || (t->lds_rows > 0 && t->lds_rows < 16) || t->levels_per_pass < 1 ||
-      t->levels_per_pass > kMaxRangeLevels || (t->persistent != 0 && t->persistent != 1))
+      t->levels_per_pass > kMaxRangeLevels || (t->persistent != 0 && t->persistent != 1) ||
+      (t->waves_per_group != kWavesLarge && t->waves_per_group != kWavesSmall))
     return fail(ctx, FFA_ERR_INVALID_ARG,
-                "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4, persistent 0 or 1");
+                "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4, persistent 0 or 1, "
+                "waves_per_group 8 or 16");
   ctx->tiling.lds_rows = t->lds_rows;
   ctx->tiling.levels_per_pass = t->levels_per_pass;
   ctx->tiling.persistent = t->persistent;
+  ctx->tiling.waves = t->waves_per_group;
   return FFA_OK;
 }
 
@@ -856,15 +866,122 @@ ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset) {
 ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                         const int64_t* nsamp, const ffa_search_params* params,
                         const char* cache_path, ffa_tiling* best, void* stream) {
-  (void)ctx;
-  (void)nseries;
-  (void)series;
-  (void)nsamp;
-  (void)params;
-  (void)cache_path;
-  (void)best;
-  (void)stream;
-  return FFA_ERR_NOT_IMPLEMENTED;
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  ffa_status st = check_batch_args(ctx, nseries, series, nsamp, params);
+  if (st != FFA_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  // key of the batch's shape: everything that changes the tile tables
+  std::string shape;
+  {
+    std::ostringstream k;
+    k << nseries << '|';
+    for (int i = 0; i < nseries; ++i)
+      k << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char c : k.str()) h = (h ^ c) * 1099511628211ull;
+    char buf[32];
+    snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    shape = buf;
+  }
+  auto report = [&](const Tiling& t) {
+    ctx->tiling = t;
+    if (best) {
+      best->lds_rows = t.lds_rows;
+      best->levels_per_pass = t.levels_per_pass;
+      best->persistent = t.persistent;
+      best->waves_per_group = t.waves;
+    }
+  };
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char key[64];
+      int lr, lv, pe, wv;
+      bool hit = false;
+      Tiling t;
+      while (fscanf(f, "%63s %d %d %d %d", key, &lr, &lv, &pe, &wv) == 5) {
+        if (shape == key) {
+          t.lds_rows = lr;
+          t.levels_per_pass = lv;
+          t.persistent = pe;
+          t.waves = wv;
+          hit = true;
+        }
+      }
+      fclose(f);
+      if (hit) {
+        report(t);
+        return FFA_OK;
+      }
+    }
+  }
+  // output rows of the batch, packed
+  std::vector<int64_t> offs(nseries);
+  int64_t rows = 0;
+  for (int i = 0; i < nseries; ++i) {
+    std::shared_ptr<SeriesPlan> plan;
+    st = get_plan(ctx, params[i], nsamp[i], &plan);
+    if (st != FFA_OK) return st;
+    offs[i] = rows;
+    rows += plan->rows;
+  }
+  HIP_TRY(ctx, ctx->tune_out.reserve((size_t)rows * params[0].num_widths * 4 + 16),
+          "allocate autotune output");
+  float* out = ctx->tune_out.as<float>();
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0), "create event");
+  HIP_TRY(ctx, hipEventCreate(&e1), "create event");
+  const Tiling saved = ctx->tiling;
+  Tiling winner = saved;
+  float best_ms = 1e30f;
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  for (int waves : {kWavesSmall, kWavesLarge})
+    for (int levels : {2, 3, 4})
+      for (int persistent : {0, 1}) {
+        Tiling t;
+        t.waves = waves;
+        t.levels_per_pass = levels;
+        t.persistent = persistent;
+        t.lds_rows = 0;
+        ctx->tiling = t;
+        // first call builds the tables and warms the caches
+        st = run_batch(ctx, nseries, series, nsamp, params, offs.data(), out, rows, 0, hs);
+        if (st != FFA_OK) break;
+        float ms_total = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(ctx, hipEventRecord(e0, hs), "record event");
+          st = run_batch(ctx, nseries, series, nsamp, params, offs.data(), out, rows, 0, hs);
+          if (st != FFA_OK) break;
+          HIP_TRY(ctx, hipEventRecord(e1, hs), "record event");
+          HIP_TRY(ctx, hipEventSynchronize(e1), "synchronise event");
+          float ms = 0.0f;
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1), "read event");
+          ms_total += ms;
+        }
+        if (st != FFA_OK) break;
+        if (ms_total < best_ms) {
+          best_ms = ms_total;
+          winner = t;
+        }
+        // drop the candidate's tables: only the winner's are kept below
+        ctx->jobs.clear();
+      }
+  ctx->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FFA_OK) {
+    ctx->tiling = saved;
+    return st;
+  }
+  report(winner);
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "%s %d %d %d %d\n", shape.c_str(), winner.lds_rows, winner.levels_per_pass,
+              winner.persistent, winner.waves);
+      fclose(f);
+    }
+  }
+  return FFA_OK;
 }
 
 }  // extern "C"

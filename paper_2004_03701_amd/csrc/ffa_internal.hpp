@@ -9,9 +9,10 @@ namespace ffa {
 // Consecutive columns a lane merges per row (odd, so that the 64 lanes of a
 // wave reading consecutive column groups hit distinct LDS banks).
 constexpr int kChunk = 5;
-// Threads of a search-kernel workgroup (16 waves of 64).
-constexpr int kThreads = 1024;
-constexpr int kWaves = kThreads / 64;
+// A search-kernel workgroup has 16 waves of 64 (one per CU, all of the LDS)
+// or 8 (two per CU, half of the LDS each).
+constexpr int kWavesLarge = 16;
+constexpr int kWavesSmall = 8;
 // (row, column-group) slots a lane stages in registers per merge level.
 constexpr int kStageMax = 8;
 // Largest subtree a full tile folds; the host precomputes their schedules.
@@ -23,8 +24,9 @@ constexpr int kSnrColsMax = (kMaxBins + 63) / 64;  // phases per lane, general S
 // Largest number of merge levels in one range pass (2^L source nodes).
 constexpr int kMaxRangeLevels = 4;
 constexpr int kMetaNodes = (2 << kMaxRangeLevels) - 1;
-// LDS available to one search workgroup (gfx950: 160 KiB per CU).
+// LDS of a CU (gfx950: 160 KiB); a workgroup of w waves uses w / 16 of it.
 constexpr int kLdsBytes = 160 * 1024;
+inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWavesLarge * waves; }
 // LDS set aside for the S/N step.
 constexpr int kSnrLdsBytes = 10 * 1024;
 
@@ -46,11 +48,11 @@ inline __host__ __device__ int col_iters(int p) { return (merge_groups(p) + 63) 
 // merge tables, the range-tile metadata, the S/N arrays, an all-zero row (the
 // tail of plain copies) and a junk row (target of idle slots' writes); at most
 // `cap` when cap > 0.
-inline __host__ __device__ int rows_capacity(int p, int cap) {
+inline __host__ __device__ int rows_capacity(int p, int cap, int waves) {
   const int fixed = kSnrLdsBytes + kMetaNodes * 5 * 4 + 64 + 2 * lds_stride(p) * 4;
   const int per_row = lds_stride(p) * 4 + 3 * 4;
-  int r = (kLdsBytes - fixed) / per_row;
-  const int rs = kWaves * (kStageMax / col_iters(p));
+  int r = (wg_lds_bytes(waves) - fixed) / per_row;
+  const int rs = waves * (kStageMax / col_iters(p));
   r = r < rs ? r : rs;
   r = r < kMaxFullRows ? r : kMaxFullRows;
   if (cap > 0 && cap < r) r = cap;
@@ -96,6 +98,7 @@ struct PassArgs {
   const TileDesc* tiles;
   int32_t ntiles;
   int32_t lds_rows_cap;    // cap on the rows of a tile (0 = what fits)
+  int32_t waves;           // waves per workgroup (kWavesLarge or kWavesSmall)
   const XformDesc* xf;
   const void* in;          // downsampled series (or raw transform input)
   int32_t in_dtype;        // ffa_dtype

@@ -403,7 +403,7 @@ struct LaneOp {
 // workgroup synchronises, then the outputs are written back. Groups that
 // start past p compute the row's wrapped copy; lanes and slots with nothing
 // to write send their values to the junk row, so no step branches.
-template <int JS, int NS>
+template <int WV, int JS, int NS>
 __device__ __forceinline__ void merge_level_ns(float* rows, int p, int stride, int J,
                                                const LaneOp& op, float* junk, int nrw) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -431,25 +431,25 @@ __device__ __forceinline__ void merge_level_ns(float* rows, int p, int stride, i
   for (int slot = 0; slot < NS; ++slot) {
     const int r = sl.row(slot);
     const int c = lane + 64 * sl.iter(slot);
-    float* o = (r < nrw && c < G) ? rows + (wave + kWaves * r) * stride + c * kChunk : junk;
+    float* o = (r < nrw && c < G) ? rows + (wave + WV * r) * stride + c * kChunk : junk;
 #pragma unroll
     for (int e = 0; e < kChunk; ++e) o[e] = acc[slot][e];
   }
   __syncthreads();
 }
 
-template <int JS>
+template <int WV, int JS>
 __device__ __forceinline__ void merge_level(float* rows, int count, int p, int stride, int J,
                                             const LaneOp& op, float* junk) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
   const int need = nrw * J;
   if (need <= 4)
-    merge_level_ns<JS, 4>(rows, p, stride, J, op, junk, nrw);
+    merge_level_ns<WV, JS, 4>(rows, p, stride, J, op, junk, nrw);
   else if (need <= 8)
-    merge_level_ns<JS, 8>(rows, p, stride, J, op, junk, nrw);
+    merge_level_ns<WV, JS, 8>(rows, p, stride, J, op, junk, nrw);
   else
-    merge_level_ns<JS, kStageMax>(rows, p, stride, J, op, junk, nrw);
+    merge_level_ns<WV, JS, kStageMax>(rows, p, stride, J, op, junk, nrw);
 }
 
 // Loads rows [0, count) into LDS with their wrapped copies; lane r of each
@@ -458,12 +458,12 @@ __device__ __forceinline__ void merge_level(float* rows, int count, int p, int s
 // rows of at most 316 bins) every load of a lane is issued before its first
 // LDS store, so a tile pays one memory round trip; wider rows go four rows at
 // a time.
-template <int JS, int DT>
+template <int WV, int JS, int DT>
 __device__ __forceinline__ void load_rows(float* rows, int count, int p, int stride,
                                           const void* base, int64_t src) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
   const int width = p + kChunk - 1;
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
   if (JS == 1) {
@@ -486,7 +486,7 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
-        if (r < nrw && c < width) rows[(wave + kWaves * r) * stride + c] = v[r][k];
+        if (r < nrw && c < width) rows[(wave + WV * r) * stride + c] = v[r][k];
       }
     return;
   }
@@ -512,19 +512,19 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
-          if (rb + u < nrw && c < width) rows[(wave + kWaves * (rb + u)) * stride + c] = v[u][k];
+          if (rb + u < nrw && c < width) rows[(wave + WV * (rb + u)) * stride + c] = v[u][k];
         }
     }
   }
 }
 
 // Writes rows [0, count) of LDS to global rows dst + q * p, coalesced.
-template <int JS>
+template <int WV, int JS>
 __device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
                                            float* dst) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int nrw = count > wave ? (count - wave + kWaves - 1) / kWaves : 0;
+  const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
   if (JS == 1) {
     constexpr int KC = 5;
     float v[kStageMax][KC];
@@ -533,14 +533,14 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
-        v[r][k] = (r < nrw && c < p) ? rows[(wave + kWaves * r) * stride + c] : 0.0f;
+        v[r][k] = (r < nrw && c < p) ? rows[(wave + WV * r) * stride + c] : 0.0f;
       }
 #pragma unroll
     for (int r = 0; r < kStageMax; ++r)
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
-        if (r < nrw && c < p) dst[(int64_t)(wave + kWaves * r) * p + c] = v[r][k];
+        if (r < nrw && c < p) dst[(int64_t)(wave + WV * r) * p + c] = v[r][k];
       }
     return;
   }
@@ -552,14 +552,14 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
-          v[u][k] = (rb + u < nrw && c < p) ? rows[(wave + kWaves * (rb + u)) * stride + c] : 0.0f;
+          v[u][k] = (rb + u < nrw && c < p) ? rows[(wave + WV * (rb + u)) * stride + c] : 0.0f;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
-          if (rb + u < nrw && c < p) dst[(int64_t)(wave + kWaves * (rb + u)) * p + c] = v[u][k];
+          if (rb + u < nrw && c < p) dst[(int64_t)(wave + WV * (rb + u)) * p + c] = v[u][k];
         }
     }
   }
@@ -683,7 +683,7 @@ __device__ __forceinline__ void ring_block(const float* row, int t, int tend, in
   }
 }
 
-template <class G>
+template <int WV, class G>
 __device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, int nvalid, float* part,
                          const float* scale, float* out) {
   constexpr int NW = G::kN, RS = G::kMax + 1;
@@ -720,7 +720,7 @@ __device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, i
     for (int k = 0; k < NW; ++k) part[(sg * NW + k) * rpad + q] = best[k];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nvalid * NW; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < nvalid * NW; idx += (WV * 64)) {
     const int q = idx / NW, k = idx - q * NW;
     float v = part[k * rpad + q];
     for (int sg = 1; sg < nseg; ++sg) v = nan_max(v, part[(sg * NW + k) * rpad + q]);
@@ -730,11 +730,12 @@ __device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, i
 
 // General widths: one wave per row, lane = contiguous phases; the prefix goes
 // to a per-wave LDS array.
+template <int WV>
 __device__ __forceinline__ void snr_general(const PassArgs& a, const float* rows, int stride, int p, int nvalid,
                             float* snrbuf, const float* scale, float* out) {
   const int wmax = a.wmax, slen = p + wmax + 1;
   int snr_waves = kSnrLdsBytes / (slen * 4);
-  snr_waves = snr_waves < kWaves ? snr_waves : kWaves;
+  snr_waves = snr_waves < WV ? snr_waves : WV;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   if (wave >= snr_waves) return;
   float* S = snrbuf + wave * slen;
@@ -778,11 +779,11 @@ __device__ __forceinline__ void snr_general(const PassArgs& a, const float* rows
   }
 }
 
-template <int JS, int DT>
+template <int WV, int JS, int DT>
 __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, const XformDesc& x,
                                          unsigned char* smem) {
   const int p = x.p, stride = lds_stride(p), J = col_iters(p);
-  const int R = rows_capacity(p, a.lds_rows_cap);
+  const int R = rows_capacity(p, a.lds_rows_cap, WV);
   float* rows = reinterpret_cast<float*>(smem);
   const int ZR = R;            // all-zero row
   float* junk = rows + (R + 1) * stride;
@@ -794,16 +795,16 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   float* snrbuf = reinterpret_cast<float*>(tr + R + 5 * kMetaNodes);
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  for (int c = tid; c < stride; c += kThreads) rows[ZR * stride + c] = 0.0f;
+  for (int c = tid; c < stride; c += (WV * 64)) rows[ZR * stride + c] = 0.0f;
 
   int r0, n;
   node_geometry(x.m, t.d_dst, t.node, r0, n);
   int nrows, s_base;
-  const int q_lane = wave + kWaves * lane;  // the wave's row held by this lane
+  const int q_lane = wave + WV * lane;  // the wave's row held by this lane
 
   if (t.flags & kTileFull) {
     const int64_t base = x.in_off + (int64_t)r0 * p;
-    load_rows<JS, DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
+    load_rows<WV, JS, DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
     if (n >= 2) {
       const int32_t off = a.full_off[n];
       // schedule entries of level `lev` for the lane's row, fetched one level
@@ -828,7 +829,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
       __syncthreads();
       for (; lev >= 0; --lev) {
         const LaneOp nxt = fetch(lev - 1);
-        merge_level<JS>(rows, n, p, stride, J, cur, junk);
+        merge_level<WV, JS>(rows, n, p, stride, J, cur, junk);
         cur = nxt;
       }
     } else {
@@ -842,19 +843,19 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     __syncthreads();
     const int llast = (2 << L) - 2;
     const int total = M.off[llast] + M.hi[llast] - M.lo[llast];
-    for (int q = tid; q < total; q += kThreads) {
+    for (int q = tid; q < total; q += (WV * 64)) {
       const int h = find_node(M, L, q);
       th[q] = M.r0[h] + M.lo[h] + (q - M.off[h]);
     }
     __syncthreads();
     const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
-    load_rows<JS, FFA_F32>(rows, total, p, stride, src + x.scr_off,
+    load_rows<WV, JS, FFA_F32>(rows, total, p, stride, src + x.scr_off,
                        q_lane < total ? (int64_t)th[q_lane] * p : 0);
     for (int l = L - 1; l >= 0; --l) {
       const int last = (2 << l) - 2;
       const int cnt = M.off[last] + M.hi[last] - M.lo[last];
       __syncthreads();  // rows loaded / previous tables consumed
-      for (int q = tid; q < cnt; q += kThreads) {
+      for (int q = tid; q < cnt; q += (WV * 64)) {
         const int h = find_node(M, l, q);
         const int v = h - ((1 << l) - 1);
         const int hc = (2 << l) - 1 + 2 * v;
@@ -878,7 +879,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
         op.t = tt[q_lane];
         op.rot = tr[q_lane];
       }
-      merge_level<JS>(rows, cnt, p, stride, J, op, junk);
+      merge_level<WV, JS>(rows, cnt, p, stride, J, op, junk);
     }
     nrows = t.s1 - t.s0;
     s_base = t.s0;
@@ -886,11 +887,11 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
 
   if (!(t.flags & kTileFinal)) {
     float* dst = (t.bufs & 2) ? a.scr1 : a.scr0;
-    store_rows<JS>(rows, nrows, p, stride, dst + x.scr_off + (int64_t)(r0 + s_base) * p);
+    store_rows<WV, JS>(rows, nrows, p, stride, dst + x.scr_off + (int64_t)(r0 + s_base) * p);
     return;
   }
   if (t.flags & kTileOutRows) {
-    store_rows<JS>(rows, nrows, p, stride, a.out_rows + x.out_row0 + (int64_t)s_base * p);
+    store_rows<WV, JS>(rows, nrows, p, stride, a.out_rows + x.out_row0 + (int64_t)s_base * p);
     return;
   }
   int nvalid = x.keep - s_base;
@@ -899,21 +900,21 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   const float* scale = a.scales + x.scale_off;
   float* out = a.snr + (x.out_row0 + s_base) * a.num_widths;
   if (a.width_set == kWidthsPaper9)
-    snr_grid<GridPaper9>(rows, stride, p, nvalid, snrbuf, scale, out);
+    snr_grid<WV, GridPaper9>(rows, stride, p, nvalid, snrbuf, scale, out);
   else if (a.width_set == kWidthsDuty9)
-    snr_grid<GridDuty9>(rows, stride, p, nvalid, snrbuf, scale, out);
+    snr_grid<WV, GridDuty9>(rows, stride, p, nvalid, snrbuf, scale, out);
   else
-    snr_general(a, rows, stride, p, nvalid, snrbuf, scale, out);
+    snr_general<WV>(a, rows, stride, p, nvalid, snrbuf, scale, out);
 }
 
 // One instantiation per (column groups per lane, input storage type): JS = 1
 // needs every tile's p <= 316 (one group per lane); JS = 0 serves any p.
-template <int JS, int DT>
-__global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
+template <int WV, int JS, int DT>
+__global__ __launch_bounds__(WV * 64) void k_ffa_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc t = a.tiles[blockIdx.x];
   const XformDesc x = a.xf[t.xf];
-  ffa_tile<JS, DT>(a, t, x, smem);
+  ffa_tile<WV, JS, DT>(a, t, x, smem);
 }
 
 // Persistent form: one workgroup per CU takes tiles in ticket order. A tile of
@@ -922,11 +923,11 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(PassArgs a) {
 // tickets, so they are held by running workgroups and the wait always ends.
 // Finished tiles publish their rows with an agent-scope release before they
 // count themselves done.
-template <int JS, int DT>
-__global__ __launch_bounds__(kThreads) void k_ffa_persist(PassArgs a) {
+template <int WV, int JS, int DT>
+__global__ __launch_bounds__(WV * 64) void k_ffa_persist(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the tile layout leaves the last 64 bytes of the LDS unused (rows_capacity)
-  int* s_ticket = reinterpret_cast<int*>(smem + kLdsBytes - 16);
+  int* s_ticket = reinterpret_cast<int*>(smem + wg_lds_bytes(WV) - 16);
   // the next ticket is fetched while the current tile is processed
   int next = 0;
   if (threadIdx.x == 0) next = atomicAdd(a.ticket, 1);
@@ -956,7 +957,7 @@ __global__ __launch_bounds__(kThreads) void k_ffa_persist(PassArgs a) {
       __syncthreads();
     }
     const XformDesc x = a.xf[t.xf];
-    ffa_tile<JS, DT>(a, t, x, smem);
+    ffa_tile<WV, JS, DT>(a, t, x, smem);
     __syncthreads();
     if (threadIdx.x == 0 && t.done >= 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1020,17 +1021,52 @@ int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
   return kLdsBytes;
 }
 
-template <int JS, int DT>
+template <int WV, int JS, int DT>
 hipError_t launch_persist_t(const PassArgs& args, int grid, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_persist<JS, DT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_persist<WV, JS, DT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       wg_lds_bytes(WV));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_ffa_persist<JS, DT>), dim3(grid), dim3(kThreads), kLdsBytes, stream, args);
+  hipLaunchKernelGGL((k_ffa_persist<WV, JS, DT>), dim3(grid), dim3(WV * 64), wg_lds_bytes(WV),
+                     stream, args);
   return hipGetLastError();
+}
+
+template <int WV, int JS, int DT>
+hipError_t launch_pass_t(const PassArgs& args, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_pass<WV, JS, DT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       wg_lds_bytes(WV));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_ffa_pass<WV, JS, DT>), dim3(args.ntiles), dim3(WV * 64), wg_lds_bytes(WV),
+                     stream, args);
+  return hipGetLastError();
+}
+
+// Instantiation for the launch: workgroup size, column groups per lane (one
+// when every p <= 316) and the storage type of the input.
+template <bool kPersist>
+hipError_t dispatch(const PassArgs& args, int grid, hipStream_t stream) {
+  const bool j1 = col_iters(args.max_p) == 1;
+  const bool big = args.waves == kWavesLarge;
+#define FFA_LAUNCH(WV, JS, DT) \
+  (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream) : launch_pass_t<WV, JS, DT>(args, stream))
+#define FFA_BY_DT(WV, JS)                                                              \
+  (args.in_dtype == FFA_BF16 ? FFA_LAUNCH(WV, JS, FFA_BF16)                          \
+                             : (args.in_dtype == FFA_F16 ? FFA_LAUNCH(WV, JS, FFA_F16) \
+                                                         : FFA_LAUNCH(WV, JS, FFA_F32)))
+  if (big) return j1 ? FFA_BY_DT(kWavesLarge, 1) : FFA_BY_DT(kWavesLarge, 0);
+  return j1 ? FFA_BY_DT(kWavesSmall, 1) : FFA_BY_DT(kWavesSmall, 0);
+#undef FFA_BY_DT
+#undef FFA_LAUNCH
 }
 
 hipError_t launch_persist(const PassArgs& args, int ncounters, int grid, hipStream_t stream) {
@@ -1039,45 +1075,12 @@ hipError_t launch_persist(const PassArgs& args, int ncounters, int grid, hipStre
                      args.counters, ncounters, args.ticket);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool j1 = col_iters(args.max_p) == 1;
-  switch (args.in_dtype) {
-    case FFA_BF16:
-      return j1 ? launch_persist_t<1, FFA_BF16>(args, grid, stream)
-                : launch_persist_t<0, FFA_BF16>(args, grid, stream);
-    case FFA_F16:
-      return j1 ? launch_persist_t<1, FFA_F16>(args, grid, stream)
-                : launch_persist_t<0, FFA_F16>(args, grid, stream);
-    default:
-      return j1 ? launch_persist_t<1, FFA_F32>(args, grid, stream)
-                : launch_persist_t<0, FFA_F32>(args, grid, stream);
-  }
-}
-
-template <int JS, int DT>
-hipError_t launch_pass_t(const PassArgs& args, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_pass<JS, DT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_ffa_pass<JS, DT>), dim3(args.ntiles), dim3(kThreads), kLdsBytes, stream,
-                     args);
-  return hipGetLastError();
+  return dispatch<true>(args, grid, stream);
 }
 
 hipError_t launch_pass(const PassArgs& args, hipStream_t stream) {
   if (args.ntiles <= 0) return hipSuccess;
-  const bool j1 = col_iters(args.max_p) == 1;
-  switch (args.in_dtype) {
-    case FFA_BF16:
-      return j1 ? launch_pass_t<1, FFA_BF16>(args, stream) : launch_pass_t<0, FFA_BF16>(args, stream);
-    case FFA_F16:
-      return j1 ? launch_pass_t<1, FFA_F16>(args, stream) : launch_pass_t<0, FFA_F16>(args, stream);
-    default:
-      return j1 ? launch_pass_t<1, FFA_F32>(args, stream) : launch_pass_t<0, FFA_F32>(args, stream);
-  }
+  return dispatch<false>(args, 0, stream);
 }
 
 hipError_t launch_norm_from_stats(const double* stats, float* norm, hipStream_t stream) {

@@ -146,7 +146,9 @@ ffa_status build_series_plan(const ffa_search_params& a, int64_t nsamp, SeriesPl
   return FFA_OK;
 }
 
-int32_t rows_capacity(int32_t p, const Tiling& t) { return ffa::rows_capacity(p, t.lds_rows); }
+int32_t rows_capacity(int32_t p, const Tiling& t) {
+  return ffa::rows_capacity(p, t.lds_rows, t.waves);
+}
 
 void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n) {
   int64_t base = 0, size = m;

@@ -52,7 +52,8 @@ double trial_period(int64_t s, int64_t m, int64_t p, double tau);
 struct Tiling {
   int32_t lds_rows = 0;         // 0: the largest that fits
   int32_t levels_per_pass = 4;  // 1..kMaxRangeLevels
-  int32_t persistent = 1;       // 1: one persistent launch per group of series
+  int32_t persistent = 0;       // 1: one persistent launch per group of series
+  int32_t waves = kWavesSmall;  // waves per workgroup: 16 (one per CU) or 8 (two per CU)
 };
 
 // Rows of a p-bin profile tile that fit in one workgroup's LDS.

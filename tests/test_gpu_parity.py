@@ -61,18 +61,20 @@ def test_transform_bit_exact_on_integers(ctx, m, p):
     assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
 
 
-@pytest.mark.parametrize("lds_rows,levels", [(16, 1), (16, 2), (24, 3), (40, 4), (0, 2)])
-def test_transform_tilings_agree(ctx, lds_rows, levels):
+@pytest.mark.parametrize("lds_rows,levels,waves", [(16, 1, 16), (16, 2, 16), (24, 3, 16),
+                                                   (40, 4, 16), (0, 2, 16), (0, 4, 8),
+                                                   (16, 1, 8)])
+def test_transform_tilings_agree(ctx, lds_rows, levels, waves):
     m, p = 1500, 61
     g = np.random.default_rng(7)
     X = g.integers(-8, 9, size=(m, p)).astype(np.float64)
     ref = oracle.fold_ffa(X)
-    ffa.ffa_set_tiling(ctx, lds_rows, levels)
+    ffa.ffa_set_tiling(ctx, lds_rows, levels, waves_per_group=waves)
     try:
         out = ffa.ffa_transform(ctx, dev(X))
         torch.cuda.synchronize()
     finally:
-        ffa.ffa_set_tiling(ctx, 0, 4)
+        ffa.ffa_set_tiling(ctx)
     assert np.array_equal(out.cpu().numpy().astype(np.float64), ref)
 
 
@@ -278,30 +280,63 @@ def test_persistent_launch_equals_pass_launches(ctx):
     dev_x = [dev(x) for x in xs]
     params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
     ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
-    a, offs = ffa.ffa_search_batch(ctx, dev_x, params)
-    torch.cuda.synchronize()
-    ffa.ffa_set_tiling(ctx, 0, 4, persistent=False)
     try:
-        b, _ = ffa.ffa_search_batch(ctx, dev_x, params)
+        a, offs = ffa.ffa_search_batch(ctx, dev_x, params)
         torch.cuda.synchronize()
     finally:
-        ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
+        ffa.ffa_set_tiling(ctx)
+    b, _ = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
     assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
-@pytest.mark.parametrize("lds_rows,levels,persistent", [(32, 2, True), (64, 3, False),
-                                                        (48, 1, True), (0, 2, True)])
-def test_search_tilings_agree(ctx, lds_rows, levels, persistent):
+@pytest.mark.parametrize("lds_rows,levels,persistent,waves", [
+    (32, 2, True, 16), (64, 3, False, 16), (48, 1, True, 16), (0, 2, True, 16),
+    (0, 4, False, 8), (0, 3, True, 8), (40, 2, False, 8)])
+def test_search_tilings_agree(ctx, lds_rows, levels, persistent, waves):
     # the FFA addition tree does not depend on the tiling; the boxcar prefix
     # sums start at the segment a wave takes, so S/N agrees to FP32 rounding
     x = synth.noise(1 << 21, synth.rng(9, 2))
     cfg = synth.config_duty(64e-6, 0.5, 4.0)
     ref = run_search(ctx, x, cfg)[2]
-    ffa.ffa_set_tiling(ctx, lds_rows, levels, persistent=persistent)
+    ffa.ffa_set_tiling(ctx, lds_rows, levels, persistent=persistent, waves_per_group=waves)
     try:
         got = run_search(ctx, x, cfg)[2]
     finally:
-        ffa.ffa_set_tiling(ctx, 0, 4, persistent=True)
+        ffa.ffa_set_tiling(ctx)
     assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
     assert snr_close(got, ref.astype(np.float64)) < 2e-6
+
+
+def test_autotune_uneven_batch_and_cache(ctx, tmp_path):
+    # uneven lengths, sampling times and period ranges (the uneven-batch
+    # workload, scaled down); the tuned tiling gives the same periodogram to
+    # FP32 rounding and is read back from the cache file
+    xs, cfgs = [], []
+    for i in range(6):
+        x, cfg, _ = synth.workload5_series(i)
+        xs.append(x[: min(x.size, 1 << 21)])
+        cfgs.append(cfg)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(c.tsamp, c.period_min, c.period_max, c.bins_min, c.bins_max,
+                              c.widths) for c in cfgs]
+    ref, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    cache = str(tmp_path / "tiles.txt")
+    try:
+        best = ffa.ffa_autotune(ctx, dev_x, params, cache_path=cache)
+        assert best.waves_per_group in (8, 16) and 1 <= best.levels_per_pass <= 4
+        got, _ = ffa.ffa_search_batch(ctx, dev_x, params)
+        torch.cuda.synchronize()
+        assert snr_close(got.cpu().numpy(), ref.cpu().numpy().astype(np.float64)) < 2e-6
+        again = ffa.ffa_autotune(ctx, dev_x, params, cache_path=cache)
+        assert (again.waves_per_group, again.levels_per_pass, again.persistent) == \
+            (best.waves_per_group, best.levels_per_pass, best.persistent)
+        assert len(open(cache).read().strip().splitlines()) == 1
+    finally:
+        ffa.ffa_set_tiling(ctx)
+    i = 3
+    ref_o = oracle.search(xs[i], cfgs[i].tsamp, cfgs[i].period_min, cfgs[i].period_max,
+                          cfgs[i].bins_min, cfgs[i].bins_max, cfgs[i].widths)
+    assert snr_close(got.cpu().numpy()[offs[i]:offs[i] + ref_o.snr.shape[0]], ref_o.snr) < SNR_RTOL
