@@ -40,6 +40,13 @@ def parse():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="batch", choices=["batch", "uneven"])
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="autotune the tiling on --tune-series series first (the default tiling "
+                         "is what the tuner picks for the batch workload)")
+    ap.add_argument("--tune-series", type=int, default=16)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
@@ -75,6 +82,26 @@ def lowp(torch, x, dt):
     return out
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ffa_kernels.hip", "ffa_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2004_03701_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload, storage):
+    """HBM bytes per step of the fold kernel from the committed rocprofv3
+    counter summary, if it was taken on the kernel source as it is now."""
+    path = os.path.join(ROOT, "profiles", "fold_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_src_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_step", {}).get(f"{workload}:{storage}")
+
+
 def cpu_baseline(seconds, nsamp):
     """The FP64 oracle, as it stands, on whole series of the same workload
     until `seconds` have passed (at least one series)."""
@@ -100,15 +127,74 @@ def cpu_baseline(seconds, nsamp):
                       f"({rows} profiles x 9 widths) in {dt:.1f} s, FP64 depth-first FFA"}
 
 
+def main_uneven(a):
+    """The uneven batch (256 series of 2^20..2^24 samples, three sampling
+    times, two period ranges): autotuned tiling against the fixed default."""
+    import torch
+    import paper_2004_03701_amd as ffa
+    import synth
+    nser = a.series if a.series != 512 else 256
+    xs, prm = [], []
+    for i in range(nser):
+        x, cfg, _ = synth.workload5_series(i)
+        xs.append(torch.from_numpy(x).cuda())
+        prm.append(ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                                   cfg.bins_max, cfg.widths))
+        if (i + 1) % 64 == 0:
+            log(f"generated {i + 1}/{nser} series")
+    rows = [ffa.ffa_plan_rows(p, x.numel()) for p, x in zip(prm, xs)]
+    ctx = ffa.ffa_create(0)
+    snr = torch.empty((sum(rows), 9), dtype=torch.float32, device="cuda")
+    out = {}
+    for name in ("default", "autotuned"):
+        ffa.ffa_set_tiling(ctx)
+        if name == "autotuned":
+            t = ffa.ffa_autotune(ctx, xs, prm)
+            out["tiling"] = {"waves_per_group": t.waves_per_group,
+                             "levels_per_pass": t.levels_per_pass, "persistent": t.persistent}
+        for _ in range(a.warmup):
+            ffa.ffa_search_batch(ctx, xs, prm, snr=snr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            ffa.ffa_search_batch(ctx, xs, prm, snr=snr)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / a.steps
+        out[name] = {"ms_per_step": ms, "profiles_per_s": sum(rows) / (ms * 1e-3)}
+        log(f"{name}: {ms:.2f} ms/step")
+    ffa.ffa_destroy(ctx)
+    r = out["autotuned"]
+    print(json.dumps({
+        "metric": "trial profiles/sec (FFA+S/N), uneven batch, autotuned vs default tiling, 1 GPU",
+        "value": r["profiles_per_s"], "unit": "profiles/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{nser} series of 2^20-2^24 samples, tsamp 64/128/256 us, "
+                               "periods 0.1-1 s or 1-30 s, bins 240-259, 9 widths"},
+        "speedup_vs_default": out["default"]["ms_per_step"] / r["ms_per_step"],
+        "variants": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.workload == "uneven":
+        return main_uneven(a)
     import torch
     import paper_2004_03701_amd as ffa
     import synth
 
+    if a.calib_copy_mib:
+        src = torch.empty(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {a.calib_copy_mib} MiB done")
+        del src, dst
     nsamp = 1 << a.log2n
     cfg = synth.workload3_config()
     x32 = make_inputs(torch, a.series, nsamp)
@@ -129,6 +215,13 @@ def main():
         bins = ffa.ffa_plan_export(prm[0], nsamp)["bins"].astype(np.int64)
         snr = torch.empty((rows1 * a.series, len(cfg.widths)), dtype=torch.float32,
                           device="cuda")
+        tiling = None
+        if a.autotune:
+            k = min(a.tune_series, a.series)
+            t = ffa.ffa_autotune(ctx, series[:k], prm[:k])
+            tiling = {"waves_per_group": t.waves_per_group, "levels_per_pass": t.levels_per_pass,
+                      "persistent": t.persistent, "lds_rows": t.lds_rows}
+            log(f"variant {v}: autotuned on {k} series -> {tiling}")
         for _ in range(a.warmup):
             ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
         torch.cuda.synchronize()
@@ -144,13 +237,15 @@ def main():
         tm = ffa.ffa_read_timing(ctx, reset=True)
         ffa.ffa_set_timing(ctx, False)
         assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+        ffa.ffa_set_tiling(ctx)
         ms = 1e3 * wall / a.steps
         profiles = rows1 * a.series
         esize = 4 if v == "f32" else 2
         alg_bytes = a.series * (int(bins.sum()) * esize + rows1 * len(cfg.widths) * 4)
         fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
         res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),
-               "profiles": profiles, "alg_bytes_fold": alg_bytes, "timing": tm}
+               "profiles": profiles, "alg_bytes_fold": alg_bytes, "timing": tm,
+               "tiling": tiling}
         if fold_ms:
             res["fold_ms_per_step"] = fold_ms
             res["fold_launches_per_step"] = tm["fold_launches"] / a.steps
@@ -182,8 +277,12 @@ def main():
     }
     if "fold_alg_GBps" in r:
         ach = r["fold_alg_GBps"]
+        tb = committed_traffic("batch", head)
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": (tb / (r["fold_ms_per_step"] * 1e-3) / 1e9) if tb else None,
+                           "kernel": "k_ffa_pass (all fold launches of a step)",
+                           "fold_ms_per_step": r["fold_ms_per_step"]}
     out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "timing"}
                        for k, v in results.items()}
     if "f32" in results and head != "f32":

@@ -114,6 +114,40 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats_partial(const SeriesDev
       s += a;
       ss += a * a;
     }
+  } else if (dtype != FFA_F32 && ((uintptr_t)sd.ptr & 15) == 0) {
+    // 8 samples of 16 bits per 16-byte load
+    const uint4* v8 = static_cast<const uint4*>(sd.ptr);
+    const int64_t n8 = sd.nsamp / 8;
+    for (int64_t k = i; k < n8; k += stride) {
+      const uint4 v = v8[k];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float lo, hi;
+        if (dtype == FFA_BF16) {
+          lo = __uint_as_float(w[q] << 16);
+          hi = __uint_as_float(w[q] & 0xffff0000u);
+        } else {
+          _Float16 h0, h1;
+          const uint16_t u0 = (uint16_t)(w[q] & 0xffffu), u1 = (uint16_t)(w[q] >> 16);
+          __builtin_memcpy(&h0, &u0, 2);
+          __builtin_memcpy(&h1, &u1, 2);
+          lo = (float)h0;
+          hi = (float)h1;
+        }
+        const double d0 = (double)lo - x0, d1 = (double)hi - x0;
+        a += d0 + d1;
+        b += d0 * d0 + d1 * d1;
+      }
+      s += a;
+      ss += b;
+    }
+    for (int64_t k = n8 * 8 + i; k < sd.nsamp; k += stride) {
+      const double a = (double)load_sample(sd.ptr, dtype, k) - x0;
+      s += a;
+      ss += a * a;
+    }
   } else {
     for (int64_t k = i; k < sd.nsamp; k += stride) {
       const double a = (double)load_sample(sd.ptr, dtype, k) - x0;
