@@ -9,7 +9,7 @@
  * to check against the paper by eye: no blocking, no fusion, no reordering.
  * All arithmetic on sample values is double precision.
  *
- * Readings of the paper used here (each listed in the design doc):
+ * Readings of the paper used here, where it is silent or ambiguous:
  *   - head/tail split of an n-row block: m_h = floor(n/2), m_t = n - m_h
  *     (Sec. 2.2 only asks for "similarly sized" blocks);
  *   - nearest-integer rounding of i and j is half-up, evaluated in exact
