@@ -675,11 +675,14 @@ __device__ __forceinline__ int find_node(const Meta& M, int l, int q) {
 // sum over two repeats of P; the S/N is the best sum over n times
 // 1 / sqrt(m w var) (precomputed in FP64).
 //
-// Compiled width grids: lane = row, and the wave walks the bins of its rows
-// in step, keeping the last wmax + 1 prefix sums in a register ring, so each
-// step costs one LDS read, one add and, per width, one subtract and one max.
-// A wave may take a segment of the bins (windows starting in it); segment
-// maxima are combined through LDS.
+// Compiled width grids: lane = (row, segment of kSnrSeg window starts). The
+// lane reads the kSnrSeg + wmax - 1 bins its windows cover into registers,
+// forms their prefix sums there, and takes, per width, the best of kSnrSeg
+// differences; every (start, width) pair costs one subtract and half a
+// three-input max. All waves of the workgroup take segments, so a tile of 64
+// rows keeps 8 waves busy; segment maxima are combined through LDS. Segments
+// past bin p repeat windows of the circular profile and change nothing.
+// Rows shorter than the register window take the ring form below instead.
 // ---------------------------------------------------------------------------
 
 template <int... W>
@@ -758,6 +761,90 @@ __device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, i
     const int q = idx / NW, k = idx - q * NW;
     float v = part[k * rpad + q];
     for (int sg = 1; sg < nseg; ++sg) v = nan_max(v, part[(sg * NW + k) * rpad + q]);
+    out[idx] = v * scale[k];
+  }
+}
+
+constexpr int kSnrSeg = 32;
+
+// The register-window form needs the window of a segment that starts below p
+// to end, after one wrap, within the row's copied bins (below p + kChunk - 1),
+// and the row area to hold the partial maxima of one segment per wave.
+template <class G>
+__device__ __forceinline__ bool snr_seg_fits(int p, int nvalid, int region_floats) {
+  constexpr int NV = kSnrSeg + G::kMax - 1;
+  return p >= NV - kChunk && region_floats >= G::kN * 64 * ((nvalid + 63) >> 6);
+}
+
+template <class G, bool kWrap>
+__device__ __forceinline__ void snr_segment(const float* row, int n0, int p, float (&best)[G::kN],
+                                            float& total) {
+  constexpr int NW = G::kN, NV = kSnrSeg + G::kMax - 1;
+  float S[NV + 1];
+  S[0] = 0.0f;
+  const float* b1 = row + n0;
+  const float* b2 = row + n0 - p;
+  const int lim = p - n0;  // bins t >= lim of the window wrap to t - p
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const float v = kWrap ? (t < lim ? b1[t] : b2[t]) : b1[t];
+    S[t + 1] = S[t] + v;
+  }
+  total += S[NV];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    float b = best[k];
+#pragma unroll
+    for (int u = 0; u + 1 < kSnrSeg; u += 2)
+      b = fmaxf(b, fmaxf(S[u + G::kW[k]] - S[u], S[u + 1 + G::kW[k]] - S[u + 1]));
+    best[k] = b;
+  }
+}
+
+template <int WV, class G>
+__device__ __forceinline__ void snr_seg(float* rows, int stride, int p, int nvalid, int region_floats,
+                                        const float* scale, float* out) {
+  constexpr int NW = G::kN, NV = kSnrSeg + G::kMax - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ngroups = (nvalid + 63) >> 6;
+  const int rpad = ngroups * 64;
+  int nseg = WV / ngroups;
+  const int fit = region_floats / (NW * rpad);
+  nseg = nseg < fit ? nseg : fit;
+  const int needed = (p + kSnrSeg - 1) / kSnrSeg;
+  nseg = nseg < needed ? nseg : needed;
+  float best[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) best[k] = -INFINITY;
+  float total = 0.0f;
+  const bool active = wave < ngroups * nseg;
+  const int g = active ? wave / nseg : 0, sg = active ? wave - g * nseg : 0;
+  const int q = g * 64 + lane;
+  if (active) {
+    const float* row = rows + (q < nvalid ? q : nvalid - 1) * stride;
+    for (int n0 = sg * kSnrSeg; n0 < p; n0 += nseg * kSnrSeg) {
+      if (n0 + NV <= p)
+        snr_segment<G, false>(row, n0, p, best, total);
+      else
+        snr_segment<G, true>(row, n0, p, best, total);
+    }
+    if (total != total) {
+#pragma unroll
+      for (int k = 0; k < NW; ++k) best[k] = total;
+    }
+  }
+  __syncthreads();  // every row read: the row area takes the partial maxima
+  float* part = rows;
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) part[(sg * NW + k) * rpad + q] = best[k];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nvalid * NW; idx += (WV * 64)) {
+    const int qq = idx / NW, k = idx - qq * NW;
+    float v = part[k * rpad + qq];
+    for (int s = 1; s < nseg; ++s) v = nan_max(v, part[(s * NW + k) * rpad + qq]);
     out[idx] = v * scale[k];
   }
 }
@@ -933,11 +1020,18 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   if (nvalid <= 0) return;
   const float* scale = a.scales + x.scale_off;
   float* out = a.snr + (x.out_row0 + s_base) * a.num_widths;
-  if (a.width_set == kWidthsPaper9)
-    snr_grid<WV, GridPaper9>(rows, stride, p, nvalid, snrbuf, scale, out);
-  else if (a.width_set == kWidthsDuty9)
-    snr_grid<WV, GridDuty9>(rows, stride, p, nvalid, snrbuf, scale, out);
-  else
+  const int region = (R + 2) * stride;  // rows, zero row and junk row
+  if (a.width_set == kWidthsPaper9) {
+    if (snr_seg_fits<GridPaper9>(p, nvalid, region))
+      snr_seg<WV, GridPaper9>(rows, stride, p, nvalid, region, scale, out);
+    else
+      snr_grid<WV, GridPaper9>(rows, stride, p, nvalid, snrbuf, scale, out);
+  } else if (a.width_set == kWidthsDuty9) {
+    if (snr_seg_fits<GridDuty9>(p, nvalid, region))
+      snr_seg<WV, GridDuty9>(rows, stride, p, nvalid, region, scale, out);
+    else
+      snr_grid<WV, GridDuty9>(rows, stride, p, nvalid, snrbuf, scale, out);
+  } else
     snr_general<WV>(a, rows, stride, p, nvalid, snrbuf, scale, out);
 }
 
