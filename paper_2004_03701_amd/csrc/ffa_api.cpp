@@ -133,6 +133,7 @@ struct ffa_ctx {
   std::map<std::string, std::shared_ptr<GraphEntry>> graphs;
   DevBuf ds_buf, scr0, scr1, stats, norm, partials, flag, tune_out;
   DevBuf full_ht, full_rot, full_off;  // merge schedules of full subtrees
+  DevBuf full_pops, full_pops_off;      // their pair schedules
   DevBuf counters, ticket;              // persistent scheduler state
   int num_cus = 256;
   size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
@@ -365,6 +366,8 @@ void set_schedules(ffa_ctx* ctx, PassArgs* pa) {
   pa->full_ht = ctx->full_ht.as<uint32_t>();
   pa->full_rot = ctx->full_rot.as<uint16_t>();
   pa->full_off = ctx->full_off.as<int32_t>();
+  pa->full_pops = ctx->full_pops.as<uint32_t>();
+  pa->full_pops_off = ctx->full_pops_off.as<int32_t>();
 }
 
 hipError_t take_event(ffa_ctx* ctx, hipEvent_t* ev) {
@@ -574,8 +577,12 @@ ffa_status ffa_create(int device, ffa_ctx** out) {
   std::vector<uint16_t> rot;
   std::vector<int32_t> off;
   build_full_schedules(&ht, &rot, &off);
+  std::vector<uint32_t> pops;
+  std::vector<int32_t> pops_off;
+  build_full_pair_ops(&pops, &pops_off);
   if (upload(c->full_ht, ht) != hipSuccess || upload(c->full_rot, rot) != hipSuccess ||
-      upload(c->full_off, off) != hipSuccess) {
+      upload(c->full_off, off) != hipSuccess || upload(c->full_pops, pops) != hipSuccess ||
+      upload(c->full_pops_off, pops_off) != hipSuccess) {
     delete c;
     return FFA_ERR_DEVICE;
   }

@@ -17,6 +17,11 @@ constexpr int kWavesSmall = 8;
 constexpr int kStageMax = 8;
 // Largest subtree a full tile folds; the host precomputes their schedules.
 constexpr int kMaxFullRows = 192;
+constexpr int kMaxFullLevels = 8;  // ceil(log2(kMaxFullRows))
+// Full tiles fold their bottom nodes of at most kRegRows rows in registers
+// (cross-lane shifts by one lane); log2 of it is the most register levels.
+constexpr int kRegRows = 8;
+constexpr int kRegLevels = 3;
 // Largest number of boxcar widths and of bins per profile.
 constexpr int kMaxWidths = 32;
 constexpr int kMaxBins = 1280;
@@ -30,14 +35,17 @@ inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWav
 // LDS set aside for the S/N step.
 constexpr int kSnrLdsBytes = 10 * 1024;
 
-// Row stride in LDS (floats) of a profile of p bins. Bins p .. p + kChunk - 2
-// hold a copy of bins 0 .. kChunk - 2, so a rotated read of kChunk consecutive
-// bins starting below p never wraps. The stride covers every kChunk-column
-// group that starts below p + kChunk - 1 (those groups then compute the copy
-// themselves) and is odd, so lanes reading the same column of different rows
-// hit different banks.
+// Bins past p that a row in LDS keeps as a copy of bins 0 .. kHalo - 1, so a
+// rotated read of kChunk + 1 consecutive bins (the two rows of a merge pair)
+// starting below p never wraps.
+constexpr int kHalo = kChunk;
+
+// Row stride in LDS (floats) of a profile of p bins. The stride covers every
+// kChunk-column group that starts below p + kHalo (those groups compute the
+// copy themselves) and is odd, so lanes reading the same column of different
+// rows hit different banks.
 inline __host__ __device__ int merge_groups(int p) {
-  return (p + kChunk - 1 + kChunk - 1) / kChunk;
+  return (p + kHalo - 1) / kChunk + 1;
 }
 inline __host__ __device__ int lds_stride(int p) { return (merge_groups(p) * kChunk) | 1; }
 
@@ -119,6 +127,14 @@ struct PassArgs {
   const uint32_t* full_ht;
   const uint16_t* full_rot;
   const int32_t* full_off;
+  // Pair schedules of full subtrees: the merge operations of relative depth
+  // lev of an n-row subtree are entries full_pops_off[n * (kMaxFullLevels + 1)
+  // + lev] .. [.. + lev + 1] of full_pops, two words each: word 0 = output row
+  // a | head row of a << 8 | head row of b << 16 | tail row << 24 (row b =
+  // a + 1); word 1 = rotation of row a (row b: one more) | single << 16, a
+  // single operation having no row b.
+  const uint32_t* full_pops;
+  const int32_t* full_pops_off;
   // Persistent launches: tile tickets, per-pass completion counters, and the
   // error word (bit 1: a dependency wait gave up after spin_limit polls).
   int32_t* ticket;

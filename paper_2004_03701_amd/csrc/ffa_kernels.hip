@@ -453,7 +453,7 @@ __device__ __forceinline__ void merge_level_ns(float* rows, int p, int stride, i
     const int col0 = (lane + 64 * sl.iter(slot)) * kChunk;
     int t0 = col0 + rot;
     t0 = t0 >= p ? t0 - p : t0;
-    if (p < kChunk - 1) t0 %= p;  // rows shorter than the copy
+    if (p < kChunk) t0 %= p;  // rows shorter than the copy
     const float* hr = rows + h * stride + col0;
     const float* trow = rows + tl * stride + t0;
 #pragma unroll
@@ -486,6 +486,245 @@ __device__ __forceinline__ void merge_level(float* rows, int count, int p, int s
     merge_level_ns<WV, JS, kStageMax>(rows, p, stride, J, op, junk, nrw);
 }
 
+// ---------------------------------------------------------------------------
+// Pair merges. Where two consecutive output rows of a node share their tail
+// row (rotations k and k + 1), one lane reads kChunk + 1 bins of the tail
+// once and the head row(s), and writes both outputs: 15 LDS instructions and
+// about 24 VALU instructions per 10 outputs instead of 18 and 35 for two
+// single rows. A single (a row with no partner) writes its second output to
+// the junk row. Operation q of a level is held by lane q / WV of wave q % WV
+// as LDS byte offsets.
+// ---------------------------------------------------------------------------
+
+struct PairOp {
+  int ha, hb, t, rot4, oa, ob;
+};
+
+template <int WV, int NS>
+__device__ __forceinline__ void merge_pairs_ns(unsigned char* base, int p4, int lane20,
+                                               const PairOp& op, int nrw) {
+  float a[NS][kChunk], b[NS][kChunk];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if (r < nrw) {
+      const int ha = __builtin_amdgcn_readlane(op.ha, r);
+      const int hb = __builtin_amdgcn_readlane(op.hb, r);
+      const int tb = __builtin_amdgcn_readlane(op.t, r);
+      const int rot4 = __builtin_amdgcn_readlane(op.rot4, r);
+      unsigned tc = (unsigned)(lane20 + rot4);
+      const unsigned tw = tc - (unsigned)p4;
+      tc = tc < tw ? tc : tw;  // wrapped below p
+      const float* tr = reinterpret_cast<const float*>(base + tb + tc);
+      const float* hr = reinterpret_cast<const float*>(base + ha + lane20);
+      float tv[kChunk + 1], hv[kChunk];
+#pragma unroll
+      for (int e = 0; e <= kChunk; ++e) tv[e] = tr[e];
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) hv[e] = hr[e];
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) a[r][e] = hv[e] + tv[e];
+      if (hb == ha) {
+#pragma unroll
+        for (int e = 0; e < kChunk; ++e) b[r][e] = hv[e] + tv[e + 1];
+      } else {
+        const float* hr2 = reinterpret_cast<const float*>(base + hb + lane20);
+#pragma unroll
+        for (int e = 0; e < kChunk; ++e) b[r][e] = hr2[e] + tv[e + 1];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if (r < nrw) {
+      const int oa = __builtin_amdgcn_readlane(op.oa, r);
+      const int ob = __builtin_amdgcn_readlane(op.ob, r);
+      float* wa = reinterpret_cast<float*>(base + oa + lane20);
+      float* wb = reinterpret_cast<float*>(base + ob + lane20);
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) wa[e] = a[r][e];
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) wb[e] = b[r][e];
+    }
+  }
+  __syncthreads();
+}
+
+template <int WV>
+__device__ __forceinline__ void merge_pairs(unsigned char* base, int p4, int lane20, const PairOp& op,
+                                            int nops) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nrw = nops > wave ? (nops - wave + WV - 1) / WV : 0;
+  const int most = (nops + WV - 1) / WV;  // the same choice in every wave
+  if (most <= 2)
+    merge_pairs_ns<WV, 2>(base, p4, lane20, op, nrw);
+  else if (most <= 3)
+    merge_pairs_ns<WV, 3>(base, p4, lane20, op, nrw);
+  else
+    merge_pairs_ns<WV, 5>(base, p4, lane20, op, nrw);
+}
+
+// ---------------------------------------------------------------------------
+// Register levels of a full tile. A wave takes a bottom node of at most
+// kRegRows rows: lane l holds bins 5l .. 5l + 4 (mod p) of each row, over all
+// 64 lanes, and the node's own merges run in registers. A rotation by k <= 5
+// bins takes bins e + k < 5 from the lane itself and the rest from lane
+// l + 1 (DPP wave shift). The last lane has no right neighbour, so after L
+// levels the top L lanes are wrong; they only hold copies past the row's
+// kChunk-column groups, which is why the register levels need
+// merge_groups(p) + L <= 64.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr int ce_head(int n, int s) {
+  return (2 * (n / 2 - 1) * s + (n - 1)) / (2 * (n - 1));
+}
+__host__ __device__ constexpr int ce_tail(int n, int s) {
+  return (2 * ((n - n / 2) - 1) * s + (n - 1)) / (2 * (n - 1));
+}
+
+__device__ __forceinline__ float from_next_lane(float v) {
+  // wave_shl:1 -- lane l receives lane l + 1; the last lane receives 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+__host__ __device__ constexpr int ce_max_rotation(int n) {
+  int m = 0;
+  for (int s = 0; s < n; ++s) m = (s - ce_tail(n, s)) > m ? (s - ce_tail(n, s)) : m;
+  return m;
+}
+
+template <int OFF, int N>
+struct RegFFA {
+  static_assert(ce_max_rotation(N) <= kChunk, "register merges shift by at most one lane");
+  static __device__ __forceinline__ void run(float (&v)[kRegRows][kChunk]) {
+    constexpr int MH = N / 2, MT = N - MH;
+    RegFFA<OFF, MH>::run(v);
+    RegFFA<OFF + MH, MT>::run(v);
+    float nx[MT][kChunk];
+#pragma unroll
+    for (int r = 0; r < MT; ++r)
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) nx[r][e] = from_next_lane(v[OFF + MH + r][e]);
+    float o[N][kChunk];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+      const int i = ce_head(N, s), j = ce_tail(N, s), k = s - j;
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) {
+        const int c = e + k;
+        o[s][e] = v[OFF + i][e] + (c < kChunk ? v[OFF + MH + j][c] : nx[j][c - kChunk]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) v[OFF + s][e] = o[s][e];
+  }
+};
+template <int OFF>
+struct RegFFA<OFF, 1> {
+  static __device__ __forceinline__ void run(float (&)[kRegRows][kChunk]) {}
+};
+
+// Loads the bottom nodes at depth d_r of an n-row full tile (rows of p bins
+// starting at element `base` of the input), folds each in registers and
+// writes the rows to LDS with their copied bins.
+template <int WV, int DT>
+__device__ __forceinline__ void reg_phase(const void* in, int64_t base, int n, int p, int d_r,
+                                          float* rows, int stride) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int G = merge_groups(p);
+  int col[kChunk];
+#pragma unroll
+  for (int e = 0; e < kChunk; ++e) col[e] = (lane * kChunk + e) % p;
+  const int nodes = 1 << d_r;
+  for (int b = wave; b < nodes; b += WV) {
+    int r0b, nb;
+    node_geometry(n, d_r, b, r0b, nb);
+    if (nb == 0) continue;
+    float v[kRegRows][kChunk];
+    const int64_t rb = base + (int64_t)r0b * p;
+#pragma unroll
+    for (int r = 0; r < kRegRows; ++r)
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e)
+        v[r][e] = r < nb ? load_sample(in, DT, rb + (int64_t)r * p + col[e]) : 0.0f;
+    switch (nb) {
+      case 2: RegFFA<0, 2>::run(v); break;
+      case 3: RegFFA<0, 3>::run(v); break;
+      case 4: RegFFA<0, 4>::run(v); break;
+      case 5: RegFFA<0, 5>::run(v); break;
+      case 6: RegFFA<0, 6>::run(v); break;
+      case 7: RegFFA<0, 7>::run(v); break;
+      case 8: RegFFA<0, 8>::run(v); break;
+      default: break;
+    }
+    if (lane < G) {
+#pragma unroll
+      for (int r = 0; r < kRegRows; ++r) {
+        if (r < nb) {
+          float* o = rows + (r0b + r) * stride + lane * kChunk;
+#pragma unroll
+          for (int e = 0; e < kChunk; ++e) o[e] = v[r][e];
+        }
+      }
+    }
+  }
+}
+
+// A full tile of n rows with one column group per lane: register levels up
+// to nodes of at most kRegRows rows, then pair merges in LDS with the host's
+// pair schedule. Needs merge_groups(p) + kRegLevels <= 64.
+template <int WV, int DT>
+__device__ __forceinline__ void full_tile_pairs(const PassArgs& a, int64_t base, int n, int p,
+                                                int stride, float* rows, int R) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int G = merge_groups(p);
+  int d_r = 0;
+  while (((n + (1 << d_r) - 1) >> d_r) > kRegRows) ++d_r;
+  reg_phase<WV, DT>(a.in, base, n, p, d_r, rows, stride);
+  if (d_r == 0) {
+    __syncthreads();
+    return;
+  }
+  const int stride4 = stride * 4, p4 = p * 4;
+  // lanes past the row's column groups repeat a group (same reads, same
+  // values written to the same place)
+  const int lane20 = (lane < G ? lane : lane % G) * kChunk * 4;
+  const int junk4 = (R + 1) * stride4;
+  const int32_t* offs = a.full_pops_off + n * (kMaxFullLevels + 1);
+  auto fetch = [&](int lev) {
+    PairOp op{0, 0, 0, 0, junk4, junk4};
+    if (lev >= 0) {
+      const int o0 = offs[lev], cnt = offs[lev + 1] - o0;
+      const int q = wave + WV * lane;
+      if (q < cnt) {
+        const uint32_t w0 = a.full_pops[2 * (o0 + q)], w1 = a.full_pops[2 * (o0 + q) + 1];
+        op.oa = (int)(w0 & 255u) * stride4;
+        op.ha = (int)((w0 >> 8) & 255u) * stride4;
+        op.hb = (int)((w0 >> 16) & 255u) * stride4;
+        op.t = (int)(w0 >> 24) * stride4;
+        int rot = (int)(w1 & 0xffffu);
+        if (rot >= p) rot %= p;
+        op.rot4 = rot * 4;
+        op.ob = (w1 >> 16) & 1u ? junk4 : op.oa + stride4;
+      }
+    }
+    return op;
+  };
+  int lev = d_r - 1;
+  PairOp cur = fetch(lev);
+  __syncthreads();  // the register levels' rows are in LDS
+  for (; lev >= 0; --lev) {
+    const PairOp nxt = fetch(lev - 1);
+    merge_pairs<WV>(reinterpret_cast<unsigned char*>(rows), p4, lane20, cur,
+                    offs[lev + 1] - offs[lev]);
+    cur = nxt;
+  }
+}
+
 // Loads rows [0, count) into LDS with their wrapped copies; lane r of each
 // wave holds in `src` the element offset of the wave's row r. Lanes take
 // consecutive columns (coalesced). With one column group per lane (JS = 1,
@@ -498,10 +737,10 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
-  const int width = p + kChunk - 1;
+  const int width = p + kHalo;
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
   if (JS == 1) {
-    constexpr int KC = 5;  // 5 x 64 columns >= p + kChunk - 1 for p <= 316
+    constexpr int KC = 5;  // 5 x 64 columns >= p + kHalo whenever one group per lane suffices
     float v[kStageMax][KC];
 #pragma unroll
     for (int r = 0; r < kStageMax; ++r) {
@@ -923,7 +1162,11 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   int nrows, s_base;
   const int q_lane = wave + WV * lane;  // the wave's row held by this lane
 
-  if (t.flags & kTileFull) {
+  if ((t.flags & kTileFull) && JS == 1 && merge_groups(p) + kRegLevels <= 64) {
+    full_tile_pairs<WV, DT>(a, x.in_off + (int64_t)r0 * p, n, p, stride, rows, R);
+    nrows = n;
+    s_base = 0;
+  } else if (t.flags & kTileFull) {
     const int64_t base = x.in_off + (int64_t)r0 * p;
     load_rows<WV, JS, DT>(rows, n, p, stride, a.in, base + (int64_t)q_lane * p);
     if (n >= 2) {
@@ -1038,7 +1281,8 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
 // One instantiation per (column groups per lane, input storage type): JS = 1
 // needs every tile's p <= 316 (one group per lane); JS = 0 serves any p.
 template <int WV, int JS, int DT>
-__global__ __launch_bounds__(WV * 64) void k_ffa_pass(PassArgs a) {
+// Four waves per SIMD: two 8-wave workgroups (or one of 16) per CU, 128 VGPRs.
+__global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_ffa_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc t = a.tiles[blockIdx.x];
   const XformDesc x = a.xf[t.xf];
@@ -1052,7 +1296,7 @@ __global__ __launch_bounds__(WV * 64) void k_ffa_pass(PassArgs a) {
 // Finished tiles publish their rows with an agent-scope release before they
 // count themselves done.
 template <int WV, int JS, int DT>
-__global__ __launch_bounds__(WV * 64) void k_ffa_persist(PassArgs a) {
+__global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_ffa_persist(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the tile layout leaves the last 64 bytes of the LDS unused (rows_capacity)
   int* s_ticket = reinterpret_cast<int*>(smem + wg_lds_bytes(WV) - 16);

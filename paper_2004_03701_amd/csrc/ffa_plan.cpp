@@ -202,6 +202,40 @@ void build_full_schedules(std::vector<uint32_t>* ht, std::vector<uint16_t>* rot,
   }
 }
 
+void build_full_pair_ops(std::vector<uint32_t>* ops, std::vector<int32_t>* off) {
+  constexpr int K = kMaxFullLevels + 1;
+  ops->clear();
+  off->assign((size_t)(kMaxFullRows + 1) * K, 0);
+  for (int n = 2; n <= kMaxFullRows; ++n) {
+    int levels = 0;
+    while ((1 << levels) < n) ++levels;
+    for (int lev = 0; lev < K; ++lev) {
+      (*off)[(size_t)n * K + lev] = (int32_t)(ops->size() / 2);
+      if (lev >= levels) continue;
+      for (int64_t b = 0; b < ((int64_t)1 << lev); ++b) {
+        int64_t b0, sz;
+        node_geometry(n, lev, b, &b0, &sz);
+        if (sz < 2) continue;  // a one-row block stays in place
+        const int64_t mh = sz / 2;
+        int64_t s = 0;
+        while (s < sz) {
+          int64_t i, j, i2 = -1, j2 = -1;
+          merge_indices(sz, s, &i, &j);
+          if (s + 1 < sz) merge_indices(sz, s + 1, &i2, &j2);
+          const bool pair = s + 1 < sz && j2 == j;
+          const uint32_t w0 = (uint32_t)(b0 + s) | ((uint32_t)(b0 + i) << 8) |
+                              ((uint32_t)(b0 + (pair ? i2 : i)) << 16) |
+                              ((uint32_t)(b0 + mh + j) << 24);
+          const uint32_t w1 = (uint32_t)(s - j) | (pair ? 0u : (1u << 16));
+          ops->push_back(w0);
+          ops->push_back(w1);
+          s += pair ? 2 : 1;
+        }
+      }
+    }
+  }
+}
+
 int32_t width_set_of(const int32_t* w, int32_t n) {
   static const int32_t paper[9] = {1, 2, 3, 4, 6, 9, 13, 19, 28};
   static const int32_t duty[9] = {1, 2, 3, 5, 8, 12, 19, 30, 48};

@@ -69,6 +69,11 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
 void build_full_schedules(std::vector<uint32_t>* ht, std::vector<uint16_t>* rot,
                           std::vector<int32_t>* off);
 
+// Pair schedules of full subtrees of 2..kMaxFullRows rows (PassArgs):
+// consecutive output rows of a node that share their tail row (rotations k
+// and k + 1) form one operation; a row without such a partner is a single.
+void build_full_pair_ops(std::vector<uint32_t>* ops, std::vector<int32_t>* off);
+
 // Compiled width grid matching `widths`, or kWidthsGeneral.
 int32_t width_set_of(const int32_t* widths, int32_t n);
 
