@@ -29,6 +29,8 @@ constexpr int kSnrColsMax = (kMaxBins + 63) / 64;  // phases per lane, general S
 // Largest number of merge levels in one range pass (2^L source nodes).
 constexpr int kMaxRangeLevels = 4;
 constexpr int kMetaNodes = (2 << kMaxRangeLevels) - 1;
+// Range-tile metadata in LDS: six arrays over the nodes, one over the levels.
+constexpr int kMetaInts = 6 * kMetaNodes + kMaxRangeLevels + 4;
 // LDS of a CU (gfx950: 160 KiB); a workgroup of w waves uses w / 16 of it.
 constexpr int kLdsBytes = 160 * 1024;
 inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWavesLarge * waves; }
@@ -57,7 +59,7 @@ inline __host__ __device__ int col_iters(int p) { return (merge_groups(p) + 63) 
 // tail of plain copies) and a junk row (target of idle slots' writes); at most
 // `cap` when cap > 0.
 inline __host__ __device__ int rows_capacity(int p, int cap, int waves) {
-  const int fixed = kSnrLdsBytes + kMetaNodes * 5 * 4 + 64 + 2 * lds_stride(p) * 4;
+  const int fixed = kSnrLdsBytes + kMetaInts * 4 + 64 + 2 * lds_stride(p) * 4;
   const int per_row = lds_stride(p) * 4 + 3 * 4;
   int r = (wg_lds_bytes(waves) - fixed) / per_row;
   const int rs = waves * (kStageMax / col_iters(p));

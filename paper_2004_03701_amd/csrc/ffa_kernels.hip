@@ -393,6 +393,27 @@ __device__ __forceinline__ void merge_indices(int n, int s, int& i, int& j) {
   j = (int)qj;
 }
 
+// The same, for blocks of at most 32768 rows: an FP32 reciprocal estimate of
+// the quotient (off by at most one) and an exact fix-up in 32-bit integers.
+__device__ __forceinline__ void merge_indices_fast(int n, int s, int& i, int& j) {
+  if (n > 32768) {
+    merge_indices(n, s, i, j);
+    return;
+  }
+  const int mh = n >> 1, mt = n - mh;
+  const unsigned den = 2u * (unsigned)(n - 1);
+  const unsigned ni = 2u * (unsigned)(mh - 1) * (unsigned)s + (unsigned)(n - 1);
+  const unsigned nj = 2u * (unsigned)(mt - 1) * (unsigned)s + (unsigned)(n - 1);
+  const float rd = __builtin_amdgcn_rcpf((float)den);
+  unsigned qi = (unsigned)((float)ni * rd), qj = (unsigned)((float)nj * rd);
+  if (qi * den > ni) --qi;
+  if ((qi + 1) * den <= ni) ++qi;
+  if (qj * den > nj) --qj;
+  if ((qj + 1) * den <= nj) ++qj;
+  i = (int)qi;
+  j = (int)qj;
+}
+
 __device__ __forceinline__ void node_geometry(int m, int d, int node, int& r0, int& n) {
   int base = 0, size = m;
   for (int b = d - 1; b >= 0; --b) {
@@ -560,8 +581,10 @@ __device__ __forceinline__ void merge_pairs(unsigned char* base, int p4, int lan
     merge_pairs_ns<WV, 2>(base, p4, lane20, op, nrw);
   else if (most <= 3)
     merge_pairs_ns<WV, 3>(base, p4, lane20, op, nrw);
-  else
+  else if (most <= 5)
     merge_pairs_ns<WV, 5>(base, p4, lane20, op, nrw);
+  else
+    merge_pairs_ns<WV, 8>(base, p4, lane20, op, nrw);
 }
 
 // ---------------------------------------------------------------------------
@@ -840,14 +863,28 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
 
 // Range-tile metadata: node h of the tile's subtree (heap order, level l holds
 // nodes (1 << l) - 1 ...), fields r0 (first row in the transform), n (rows),
-// [lo, hi) rows kept, off (position of row lo in LDS).
+// [lo, hi) rows kept, off (position of row lo in LDS), ooff (first pair
+// operation of the node within its level); lops[l] = operations of level l.
 struct Meta {
   int* r0;
   int* n;
   int* lo;
   int* hi;
   int* off;
+  int* ooff;
+  int* lops;
 };
+
+// Pair operations of node rows [lo, hi) of an n-row node (n >= 2): rows s and
+// s + 1 share their tail row when s is even (n even) or odd (n odd), so a
+// leading row of the other parity and a trailing unpaired row are singles.
+__device__ __forceinline__ int node_pair_ops(int n, int lo, int hi) {
+  if (hi <= lo || n <= 0) return 0;
+  if (n == 1) return 1;
+  const int lead = ((lo & 1) != (n & 1)) ? 1 : 0;
+  const int rem = hi - lo - lead;
+  return lead + (rem >> 1) + (rem & 1);
+}
 
 // Built by wave 0: lane v handles node v of a level.
 __device__ __forceinline__ void build_meta(Meta M, int r0, int n, int s0, int s1, int L) {
@@ -880,8 +917,8 @@ __device__ __forceinline__ void build_meta(Meta M, int r0, int n, int s0, int s1
       } else {
         const int mh = pn >> 1;
         int i0, j0, i1, j1;
-        merge_indices(pn, plo, i0, j0);
-        merge_indices(pn, phi - 1, i1, j1);
+        merge_indices_fast(pn, plo, i0, j0);
+        merge_indices_fast(pn, phi - 1, i1, j1);
         M.r0[hc] = M.r0[h];
         M.n[hc] = mh;
         M.lo[hc] = i0;
@@ -892,6 +929,14 @@ __device__ __forceinline__ void build_meta(Meta M, int r0, int n, int s0, int s1
         M.hi[hc + 1] = j1 + 1;
       }
     }
+    {
+      const int ops = lane < (1 << l) ? node_pair_ops(M.n[(1 << l) - 1 + lane], M.lo[(1 << l) - 1 + lane],
+                                                      M.hi[(1 << l) - 1 + lane])
+                                      : 0;
+      const int incl = wave_inclusive_sum(ops, lane);
+      if (lane < (1 << l)) M.ooff[(1 << l) - 1 + lane] = incl - ops;
+      if (lane == 63) M.lops[l] = incl;
+    }
     wave_lds_sync();
     const int len = lane < (2 << l) ? M.hi[cfirst + lane] - M.lo[cfirst + lane] : 0;
     const int incl = wave_inclusive_sum(len, lane);
@@ -900,7 +945,174 @@ __device__ __forceinline__ void build_meta(Meta M, int r0, int n, int s0, int s1
   }
 }
 
+// The same metadata with every node computed at once: lane h (heap index)
+// walks from the tile's node down its path, the row and operation offsets
+// are scans within each level. One wave, no LDS round trips between levels.
+__device__ __forceinline__ void build_meta_par(Meta M, int r0, int n, int s0, int s1, int L) {
+  const int lane = threadIdx.x & 63;
+  const int nn = (2 << L) - 1;
+  int hr0 = r0, hn = n, hlo = s0, hhi = s1, lev = 0;
+  if (lane < nn) {
+    lev = 31 - __builtin_clz(lane + 1);
+    const int v = lane + 1 - (1 << lev);
+    for (int b = lev - 1; b >= 0; --b) {
+      const bool right = (v >> b) & 1;
+      if (hhi <= hlo || hn == 0) {
+        hn = 0;
+        hlo = hhi = 0;
+      } else if (hn == 1) {  // a one-row block: its tail child is the row
+        hn = right ? 1 : 0;
+        hlo = 0;
+        hhi = right ? 1 : 0;
+      } else {
+        const int mh = hn >> 1;
+        int i0, j0, i1, j1;
+        merge_indices_fast(hn, hlo, i0, j0);
+        merge_indices_fast(hn, hhi - 1, i1, j1);
+        if (right) {
+          hr0 += mh;
+          hn -= mh;
+          hlo = j0;
+          hhi = j1 + 1;
+        } else {
+          hn = mh;
+          hlo = i0;
+          hhi = i1 + 1;
+        }
+      }
+    }
+  }
+  const int len = lane < nn ? hhi - hlo : 0;
+  const int ops = (lane < nn && lev < L) ? node_pair_ops(hn, hlo, hhi) : 0;
+  const int incl_len = wave_inclusive_sum(len, lane);
+  const int incl_ops = wave_inclusive_sum(ops, lane);
+  const int first = (1 << lev) - 1;  // first node of the lane's level
+  const int before_len = __shfl(incl_len, first > 0 ? first - 1 : 0, 64);
+  const int before_ops = __shfl(incl_ops, first > 0 ? first - 1 : 0, 64);
+  if (lane < nn) {
+    M.r0[lane] = hr0;
+    M.n[lane] = hn;
+    M.lo[lane] = hlo;
+    M.hi[lane] = hhi;
+    M.off[lane] = incl_len - len - (first > 0 ? before_len : 0);
+    M.ooff[lane] = incl_ops - ops - (first > 0 ? before_ops : 0);
+    if (lane == (2 << lev) - 2 && lev < L) M.lops[lev] = incl_ops - (first > 0 ? before_ops : 0);
+  }
+}
+
 // Node (heap index) of level l holding position q.
+__device__ __forceinline__ int find_node(const Meta& M, int l, int q);
+
+// A range tile with one column group per lane: the node metadata (wave 0),
+// then every level's pair operations at once (all threads, LDS byte offsets
+// into `ops`, six ints each), the rows L levels below from scratch, and L
+// pair-merge levels. Needs merge_groups(p) <= 64.
+template <int WV>
+__device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDesc& t, const XformDesc& x,
+                                                 int r0, int n, int p, int stride, float* rows, int R,
+                                                 const Meta& M, int* th, int* ops) {
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int L = t.levels;
+  const int G = merge_groups(p);
+  const int stride4 = stride * 4, p4 = p * 4;
+  const int junk4 = (R + 1) * stride4, zero4 = R * stride4;
+  if (wave == 0) build_meta_par(M, r0, n, t.s0, t.s1, L);
+  __syncthreads();
+  int lbase[kMaxRangeLevels + 1];
+  lbase[0] = 0;
+#pragma unroll
+  for (int l = 0; l < kMaxRangeLevels; ++l) lbase[l + 1] = lbase[l] + (l < L ? M.lops[l] : 0);
+  const int llast = (2 << L) - 2;
+  const int total = M.off[llast] + M.hi[llast] - M.lo[llast];
+  constexpr int kThreads = WV * 64;
+  {
+    // source rows: a fixed share of the threads per node of level L
+    const int slots = kThreads >> L;
+    const int h = (1 << L) - 1 + tid / slots;
+    const int len = M.hi[h] - M.lo[h], base = M.r0[h] + M.lo[h], off = M.off[h];
+    for (int k = tid % slots; k < len; k += slots) th[off + k] = base + k;
+  }
+  // pair operations: kThreads / kMaxRangeLevels threads per level, an equal
+  // share of them per node of the level
+  constexpr int kPerLevel = kThreads / kMaxRangeLevels;
+  const int l = tid / kPerLevel;
+  if (l < L) {
+    const int slots = kPerLevel >> l;
+    const int v = (tid % kPerLevel) / slots;
+    const int h = (1 << l) - 1 + v, hc = (2 << l) - 1 + 2 * v;
+    // the node's and its children's fields, read together
+    const int pn = M.n[h], plo = M.lo[h], phi = M.hi[h], hoff = M.off[h], hooff = M.ooff[h];
+    const int hc_off = M.off[hc], hc_lo = M.lo[hc], tc_off = M.off[hc + 1], tc_lo = M.lo[hc + 1];
+    const int nops = node_pair_ops(pn, plo, phi);
+    const int lead = ((plo & 1) != (pn & 1)) ? 1 : 0;
+    const int rem = phi - plo - lead;
+    for (int kk = tid % slots; kk < nops; kk += slots) {
+      int* e = ops + 6 * (lbase[l] + hooff + kk);
+      if (pn == 1) {  // a one-row block: its tail child's only row, copied
+        e[0] = e[1] = tc_off * stride4;
+        e[2] = zero4;
+        e[3] = 0;
+        e[4] = hoff * stride4;
+        e[5] = junk4;
+        continue;
+      }
+      int s;
+      bool single;
+      if (kk < lead) {
+        s = plo;
+        single = true;
+      } else {
+        const int q2 = 2 * (kk - lead);
+        s = plo + lead + q2;
+        single = q2 + 1 >= rem;
+      }
+      int i, j, hb, j2;
+      merge_indices_fast(pn, s, i, j);
+      merge_indices_fast(pn, single ? s : s + 1, hb, j2);
+      int rot = s - j;
+      if (rot >= p) rot %= p;
+      const int oa = hoff + (s - plo);
+      e[0] = (hc_off + (i - hc_lo)) * stride4;
+      e[1] = (hc_off + (hb - hc_lo)) * stride4;
+      e[2] = (tc_off + (j - tc_lo)) * stride4;
+      e[3] = rot * 4;
+      e[4] = oa * stride4;
+      e[5] = single ? junk4 : (oa + 1) * stride4;
+    }
+  }
+  __syncthreads();
+  const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
+  const int q_lane = wave + WV * lane;
+  load_rows<WV, 1, FFA_F32>(rows, total, p, stride, src + x.scr_off,
+                            q_lane < total ? (int64_t)th[q_lane] * p : 0);
+  const int lane20 = (lane < G ? lane : lane % G) * kChunk * 4;
+  auto fetch = [&](int l) {
+    PairOp op{0, 0, 0, 0, junk4, junk4};
+    if (l >= 0) {
+      const int q = wave + WV * lane;
+      if (q < lbase[l + 1] - lbase[l]) {
+        const int* e = ops + 6 * (lbase[l] + q);
+        op.ha = e[0];
+        op.hb = e[1];
+        op.t = e[2];
+        op.rot4 = e[3];
+        op.oa = e[4];
+        op.ob = e[5];
+      }
+    }
+    return op;
+  };
+  PairOp cur = fetch(L - 1);
+  __syncthreads();  // rows loaded
+  for (int l = L - 1; l >= 0; --l) {
+    const PairOp nxt = fetch(l - 1);
+    merge_pairs<WV>(reinterpret_cast<unsigned char*>(rows), p4, lane20, cur, lbase[l + 1] - lbase[l]);
+    cur = nxt;
+  }
+}
+
+
 __device__ __forceinline__ int find_node(const Meta& M, int l, int q) {
   const int first = (1 << l) - 1;
   int v = 0;
@@ -1150,9 +1362,16 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   int* th = reinterpret_cast<int*>(rows + (R + 2) * stride);
   int* tt = th + R;
   int* tr = tt + R;
-  Meta M{tr + R, tr + R + kMetaNodes, tr + R + 2 * kMetaNodes, tr + R + 3 * kMetaNodes,
-         tr + R + 4 * kMetaNodes};
-  float* snrbuf = reinterpret_cast<float*>(tr + R + 5 * kMetaNodes);
+  Meta M{tr + R,
+         tr + R + kMetaNodes,
+         tr + R + 2 * kMetaNodes,
+         tr + R + 3 * kMetaNodes,
+         tr + R + 4 * kMetaNodes,
+         tr + R + 5 * kMetaNodes,
+         tr + R + 6 * kMetaNodes};
+  // the S/N scratch; range tiles keep their pair operations here until the
+  // merges are done
+  float* snrbuf = reinterpret_cast<float*>(tr + R + kMetaInts);
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int c = tid; c < stride; c += (WV * 64)) rows[ZR * stride + c] = 0.0f;
@@ -1201,6 +1420,11 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     }
     nrows = n;
     s_base = 0;
+  } else if (JS == 1 && merge_groups(p) <= 64) {
+    range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, th,
+                         reinterpret_cast<int*>(snrbuf));
+    nrows = t.s1 - t.s0;
+    s_base = t.s0;
   } else {
     const int L = t.levels;
     if (wave == 0) build_meta(M, r0, n, t.s0, t.s1, L);
