@@ -814,6 +814,40 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
   }
 }
 
+// load_rows for one column group per lane and FP32 rows, with `work` run
+// between the loads and the LDS stores (while the loads are in flight).
+template <int WV, class F>
+__device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p, int stride,
+                                                  const float* base, int64_t src, F&& work) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
+  const int width = p + kHalo;
+  const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
+  constexpr int KC = 5;
+  float v[kStageMax][KC];
+#pragma unroll
+  for (int r = 0; r < kStageMax; ++r) {
+    const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
+                      ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      int col = c < p ? c : c - p;
+      if (col >= p) col %= p;
+      v[r][k] = (r < nrw && c < width) ? base[g + col] : 0.0f;
+    }
+  }
+  work();
+#pragma unroll
+  for (int r = 0; r < kStageMax; ++r)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      if (r < nrw && c < width) rows[(wave + WV * r) * stride + c] = v[r][k];
+    }
+}
+
 // Writes rows [0, count) of LDS to global rows dst + q * p, coalesced.
 template <int WV, int JS>
 __device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
@@ -1033,8 +1067,14 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
     const int len = M.hi[h] - M.lo[h], base = M.r0[h] + M.lo[h], off = M.off[h];
     for (int k = tid % slots; k < len; k += slots) th[off + k] = base + k;
   }
-  // pair operations: kThreads / kMaxRangeLevels threads per level, an equal
+  __syncthreads();
+  const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
+  const int q_lane = wave + WV * lane;
+  // the source rows' loads are in flight while the pair operations of every
+  // level are built: kThreads / kMaxRangeLevels threads per level, an equal
   // share of them per node of the level
+  load_rows_overlap<WV>(rows, total, p, stride, src + x.scr_off,
+                        q_lane < total ? (int64_t)th[q_lane] * p : 0, [&]() {
   constexpr int kPerLevel = kThreads / kMaxRangeLevels;
   const int l = tid / kPerLevel;
   if (l < L) {
@@ -1081,11 +1121,7 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
       e[5] = single ? junk4 : (oa + 1) * stride4;
     }
   }
-  __syncthreads();
-  const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
-  const int q_lane = wave + WV * lane;
-  load_rows<WV, 1, FFA_F32>(rows, total, p, stride, src + x.scr_off,
-                            q_lane < total ? (int64_t)th[q_lane] * p : 0);
+  });
   const int lane20 = (lane < G ? lane : lane % G) * kChunk * 4;
   auto fetch = [&](int l) {
     PairOp op{0, 0, 0, 0, junk4, junk4};
@@ -1103,8 +1139,8 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
     }
     return op;
   };
+  __syncthreads();  // rows loaded, pair operations built
   PairOp cur = fetch(L - 1);
-  __syncthreads();  // rows loaded
   for (int l = L - 1; l >= 0; --l) {
     const PairOp nxt = fetch(l - 1);
     merge_pairs<WV>(reinterpret_cast<unsigned char*>(rows), p4, lane20, cur, lbase[l + 1] - lbase[l]);
@@ -1554,11 +1590,11 @@ __global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
     const XformDesc x = a.xf[t.xf];
     ffa_tile<WV, JS, DT>(a, t, x, smem);
+    // every wave publishes its own global stores before the tile counts
+    // itself done
+    if (t.done >= 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0 && t.done >= 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      atomicAdd(a.counters + t.done, 1);
-    }
+    if (threadIdx.x == 0 && t.done >= 0) atomicAdd(a.counters + t.done, 1);
   }
 }
 
