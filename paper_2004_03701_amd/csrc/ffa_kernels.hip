@@ -71,6 +71,19 @@ __device__ __forceinline__ T wave_inclusive_sum(T v, int lane) {
   return v;
 }
 
+// Inclusive sum over the 64 lanes with DPP row shifts and row broadcasts
+// (no LDS traffic): shifts by 1, 2, 4, 8 within each 16-lane row, then
+// lane 15 of a row is added to the next row and lane 31 to rows 2 and 3.
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
@@ -393,8 +406,19 @@ __device__ __forceinline__ void merge_indices(int n, int s, int& i, int& j) {
   j = (int)qj;
 }
 
-// The same, for blocks of at most 32768 rows: an FP32 reciprocal estimate of
-// the quotient (off by at most one) and an exact fix-up in 32-bit integers.
+// nint(k s / (n - 1)), ties up, for blocks of at most 32768 rows (k = m_h - 1
+// gives i, k = m_t - 1 gives j): an FP32 reciprocal estimate of the quotient
+// (off by at most one) and an exact fix-up in 32-bit integers.
+__device__ __forceinline__ int merge_index_small(int n, int k, int s) {
+  const unsigned den = 2u * (unsigned)(n - 1);
+  const unsigned num = 2u * (unsigned)k * (unsigned)s + (unsigned)(n - 1);
+  unsigned q = (unsigned)((float)num * __builtin_amdgcn_rcpf((float)den));
+  if (q * den > num) --q;
+  if ((q + 1) * den <= num) ++q;
+  return (int)q;
+}
+
+// Both indices; the FP64 form above past 32768 rows.
 __device__ __forceinline__ void merge_indices_fast(int n, int s, int& i, int& j) {
   if (n > 32768) {
     merge_indices(n, s, i, j);
@@ -1000,37 +1024,46 @@ __device__ __forceinline__ void build_meta_par(Meta M, int r0, int n, int s0, in
         hhi = right ? 1 : 0;
       } else {
         const int mh = hn >> 1;
-        int i0, j0, i1, j1;
-        merge_indices_fast(hn, hlo, i0, j0);
-        merge_indices_fast(hn, hhi - 1, i1, j1);
-        if (right) {
-          hr0 += mh;
-          hn -= mh;
-          hlo = j0;
-          hhi = j1 + 1;
+        const int k = right ? hn - mh - 1 : mh - 1;  // m_t - 1 or m_h - 1
+        int c0, c1;
+        if (hn <= 32768) {
+          c0 = merge_index_small(hn, k, hlo);
+          c1 = merge_index_small(hn, k, hhi - 1);
         } else {
-          hn = mh;
-          hlo = i0;
-          hhi = i1 + 1;
+          int i0, j0, i1, j1;
+          merge_indices(hn, hlo, i0, j0);
+          merge_indices(hn, hhi - 1, i1, j1);
+          c0 = right ? j0 : i0;
+          c1 = right ? j1 : i1;
         }
+        if (right) hr0 += mh;
+        hn = right ? hn - mh : mh;
+        hlo = c0;
+        hhi = c1 + 1;
       }
     }
   }
+  // rows (low half) and operations (high half) of the node, scanned together
   const int len = lane < nn ? hhi - hlo : 0;
   const int ops = (lane < nn && lev < L) ? node_pair_ops(hn, hlo, hhi) : 0;
-  const int incl_len = wave_inclusive_sum(len, lane);
-  const int incl_ops = wave_inclusive_sum(ops, lane);
-  const int first = (1 << lev) - 1;  // first node of the lane's level
-  const int before_len = __shfl(incl_len, first > 0 ? first - 1 : 0, 64);
-  const int before_ops = __shfl(incl_ops, first > 0 ? first - 1 : 0, 64);
+  const int both = len | (ops << 16);
+  const int incl = wave_scan_dpp(both);
+  // inclusive sums up to the last node of each level above (heap index 2^l - 2)
+  int before = 0;
+#pragma unroll
+  for (int l = 1; l <= kMaxRangeLevels; ++l) {
+    const int b = __builtin_amdgcn_readlane(incl, (1 << l) - 2);
+    before = lev == l ? b : before;
+  }
+  const int excl = incl - both - before;
   if (lane < nn) {
     M.r0[lane] = hr0;
     M.n[lane] = hn;
     M.lo[lane] = hlo;
     M.hi[lane] = hhi;
-    M.off[lane] = incl_len - len - (first > 0 ? before_len : 0);
-    M.ooff[lane] = incl_ops - ops - (first > 0 ? before_ops : 0);
-    if (lane == (2 << lev) - 2 && lev < L) M.lops[lev] = incl_ops - (first > 0 ? before_ops : 0);
+    M.off[lane] = excl & 0xffff;
+    M.ooff[lane] = excl >> 16;
+    if (lane == (2 << lev) - 2 && lev < L) M.lops[lev] = (incl - before) >> 16;
   }
 }
 
