@@ -32,6 +32,23 @@ __device__ __forceinline__ float load_sample(const void* base, int dtype, int64_
   return static_cast<float>(h);
 }
 
+// Global-address-space forms with the storage type fixed at compile time:
+// straight-line global loads a thread can keep in flight together (a runtime
+// type test between loads, or a generic pointer, makes the compiler wait for
+// each load in turn).
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <int DT>
+__device__ __forceinline__ float load_g(const void* base, int64_t i) {
+  if (DT == FFA_F32) return ((gptr<float>)base)[i];
+  const uint16_t b = ((gptr<uint16_t>)base)[i];
+  if (DT == FFA_BF16) return __uint_as_float(static_cast<uint32_t>(b) << 16);
+  _Float16 h;
+  __builtin_memcpy(&h, &b, 2);
+  return static_cast<float>(h);
+}
+
 __device__ __forceinline__ void store_sample(void* base, int dtype, int64_t i, float v) {
   if (dtype == FFA_F32) {
     static_cast<float*>(base)[i] = v;
@@ -81,6 +98,22 @@ __device__ __forceinline__ int wave_scan_dpp(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
   v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// The same for floats (the DPP moves carry the bits; the adds are FP32).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, kRowMask, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_scan_dpp_f32(float v) {
+  v += dpp_f32<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f32<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f32<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f32<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f32<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_f32<0x143, 0xc>(v);  // row_bcast:31
   return v;
 }
 
@@ -249,15 +282,17 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 constexpr int kDsMaxOctaves = 128;
 constexpr int kDsLoadIters = 24;  // samples a thread loads before storing (block + halo <= 24 * 512)
 
+template <int DT>
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
                                                            int32_t nseries,
                                                            const OctaveDev* oct,
-                                                           const float* norm, int dtype,
-                                                           void* out, int out_dtype) {
+                                                           const float* norm, void* out) {
   extern __shared__ float sm[];
   __shared__ int s_series;
   __shared__ float s_part[kDsThreads / 64];
   __shared__ int64_t s_j0[kDsMaxOctaves];
+  __shared__ uint64_t s_dsfx[kDsMaxOctaves];
+  __shared__ int64_t s_off[kDsMaxOctaves];
   __shared__ int s_cum[kDsMaxOctaves + 1];
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
@@ -290,7 +325,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
 #pragma unroll
     for (int k = 0; k < kDsLoadIters; ++k) {
       const int q = q0 + tid + k * kDsThreads;
-      v[k] = q < len ? load_sample(sd.ptr, dtype, c0 + q) : 0.0f;
+      v[k] = q < len ? load_g<DT>(sd.ptr, c0 + q) : 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < kDsLoadIters; ++k) {
@@ -310,6 +345,8 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
       j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
     }
     s_j0[tid] = j0;
+    s_dsfx[tid] = o.ds_fx;
+    s_off[tid] = o.off;
     s_cum[tid + 1] = j1 > j0 ? (int)(j1 - j0) : 0;  // counts, scanned below
   }
   __syncthreads();
@@ -326,12 +363,13 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     if (lane == 0) s_cum[0] = 0;
   }
   __syncthreads();
-  // exclusive prefix: contiguous segments per thread, then a block scan
-  const int seg = (len + kDsThreads - 1) / kDsThreads;
+  // exclusive prefix: contiguous segments per thread (an odd length, so the
+  // lanes' reads fall in distinct banks), then a block scan
+  const int seg = ((len + kDsThreads - 1) / kDsThreads) | 1;
   const int q0 = min(tid * seg, len), q1 = min(q0 + seg, len);
   float run = 0.0f;
   for (int q = q0; q < q1; ++q) run += xs[q];
-  float incl = wave_inclusive_sum(run, lane);
+  float incl = wave_scan_dpp_f32(run);
   if (lane == 63) s_part[wave] = incl;
   __syncthreads();
   float woff = 0.0f;
@@ -344,26 +382,32 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   if (q1 == len && q0 < q1) ps[len] = acc;
   if (len == 0 && tid == 0) ps[0] = 0.0f;
   __syncthreads();
-  // all outputs of all octaves, flattened
+  // all outputs of all octaves, flattened; the 64 outputs of a wave step
+  // share one search for their first octave, then each lane moves on past
+  // the octaves that end before its output
   const int total = s_cum[noct];
-  for (int u = tid; u < total; u += kDsThreads) {
-    int lo = 0, hi = noct - 1;  // octave k with s_cum[k] <= u < s_cum[k + 1]
+  for (int u0 = wave * 64; u0 < total; u0 += kDsThreads) {
+    int lo = 0, hi = noct - 1;  // octave k with s_cum[k] <= u0 < s_cum[k + 1]
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
-      if (s_cum[mid] <= u)
+      if (s_cum[mid] <= u0)
         lo = mid;
       else
         hi = mid - 1;
     }
-    const OctaveDev o = oct[sd.oct0 + lo];
-    const int64_t j = s_j0[lo] + (u - s_cum[lo]);
-    const uint64_t a = (uint64_t)j * o.ds_fx, b = a + o.ds_fx;
+    const int u = u0 + lane;
+    if (u >= total) continue;
+    int k = lo;
+    while (s_cum[k + 1] <= u) ++k;
+    const uint64_t dsfx = s_dsfx[k];
+    const int64_t j = s_j0[k] + (u - s_cum[k]);
+    const uint64_t a = (uint64_t)j * dsfx, b = a + dsfx;
     const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
     const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
     const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
     float y = (1.0f - fa) * xs[ia] + (ps[ib] - ps[ia + 1]);
     if ((uint32_t)b != 0u) y += fb * xs[ib];
-    store_sample(out, out_dtype, o.off + j, y * inv);
+    store_sample(out, DT, s_off[k] + j, y * inv);
   }
 }
 
@@ -1662,22 +1706,33 @@ int32_t downsample_block_samples(int32_t max_halo) {
   return b;
 }
 
-hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
-                             const float* norm, int32_t dtype, void* out, int32_t out_dtype,
-                             int64_t nblocks, int32_t lds_floats, hipStream_t stream) {
-  const size_t lds = (size_t)lds_floats * sizeof(float);
+template <int DT>
+hipError_t launch_downsample_t(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
+                               const float* norm, void* out, int64_t nblocks, size_t lds,
+                               hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample<DT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kLdsBytes - 4096);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  if (lds > (size_t)(kLdsBytes - 4096)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_downsample, dim3((unsigned)nblocks), dim3(kDsThreads), lds, stream,
-                     series_dev, nseries, oct, norm, dtype, out, out_dtype);
+  hipLaunchKernelGGL(k_downsample<DT>, dim3((unsigned)nblocks), dim3(kDsThreads), lds, stream,
+                     series_dev, nseries, oct, norm, out);
   return hipGetLastError();
+}
+
+hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
+                             const float* norm, int32_t dtype, void* out, int32_t out_dtype,
+                             int64_t nblocks, int32_t lds_floats, hipStream_t stream) {
+  const size_t lds = (size_t)lds_floats * sizeof(float);
+  if (lds > (size_t)(kLdsBytes - 4096) || out_dtype != dtype) return hipErrorInvalidValue;
+  if (dtype == FFA_BF16)
+    return launch_downsample_t<FFA_BF16>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
+  if (dtype == FFA_F16)
+    return launch_downsample_t<FFA_F16>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
+  return launch_downsample_t<FFA_F32>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
 }
 
 int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
