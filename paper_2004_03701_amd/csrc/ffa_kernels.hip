@@ -49,6 +49,39 @@ __device__ __forceinline__ float load_g(const void* base, int64_t i) {
   return static_cast<float>(h);
 }
 
+// The stored bits of sample i (FP32 bits, or 16 bits zero-extended), and
+// their value: loads kept apart from the conversion, so that loads behind a
+// condition stay in flight together.
+template <int DT>
+__device__ __forceinline__ uint32_t load_bits(const void* base, int64_t i) {
+  if (DT == FFA_F32) return __float_as_uint(((gptr<float>)base)[i]);
+  return ((gptr<uint16_t>)base)[i];
+}
+
+// The same from a uniform row start and a per-lane 32-bit column.
+template <int DT>
+__device__ __forceinline__ uint32_t load_row_bits(const void* base, int64_t row, uint32_t col) {
+  // the row start is the same in every lane and the byte offset an unsigned
+  // 32-bit value: a scalar base plus a vector offset
+  const uint32_t boff = col * (DT == FFA_F32 ? 4u : 2u);
+  if (DT == FFA_F32) {
+    gptr<unsigned char> rp = (gptr<unsigned char>)((gptr<float>)base + row);
+    return *(gptr<uint32_t>)(rp + boff);
+  }
+  gptr<unsigned char> rp = (gptr<unsigned char>)((gptr<uint16_t>)base + row);
+  return *(gptr<uint16_t>)(rp + boff);
+}
+
+template <int DT>
+__device__ __forceinline__ float bits_value(uint32_t b) {
+  if (DT == FFA_F32) return __uint_as_float(b);
+  if (DT == FFA_BF16) return __uint_as_float(b << 16);
+  const uint16_t u = (uint16_t)b;
+  _Float16 h;
+  __builtin_memcpy(&h, &u, 2);
+  return static_cast<float>(h);
+}
+
 __device__ __forceinline__ void store_sample(void* base, int dtype, int64_t i, float v) {
   if (dtype == FFA_F32) {
     static_cast<float*>(base)[i] = v;
@@ -321,16 +354,18 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   const float inv = sd.normalise ? norm[2 * si + 1] : 1.0f;
   // every load of a thread is in flight before its first LDS store
   for (int q0 = 0; q0 < len; q0 += kDsLoadIters * kDsThreads) {
-    float v[kDsLoadIters];
+    uint32_t v[kDsLoadIters];
 #pragma unroll
     for (int k = 0; k < kDsLoadIters; ++k) {
-      const int q = q0 + tid + k * kDsThreads;
-      v[k] = q < len ? load_g<DT>(sd.ptr, c0 + q) : 0.0f;
+      // unconditional (clamped) loads: no branch for the compiler to sink
+      // the conversions into
+      const int q = min(q0 + tid + k * kDsThreads, len - 1);
+      v[k] = load_bits<DT>(sd.ptr, c0 + q);
     }
 #pragma unroll
     for (int k = 0; k < kDsLoadIters; ++k) {
       const int q = q0 + tid + k * kDsThreads;
-      if (q < len) xs[q] = v[k] - mean;
+      if (q < len) xs[q] = bits_value<DT>(v[k]) - mean;
     }
   }
   // window ranges of every octave, one octave per thread: outputs whose
@@ -386,15 +421,9 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   // share one search for their first octave, then each lane moves on past
   // the octaves that end before its output
   const int total = s_cum[noct];
+  int lo = 0;  // octave of the wave's first output; only moves forward
   for (int u0 = wave * 64; u0 < total; u0 += kDsThreads) {
-    int lo = 0, hi = noct - 1;  // octave k with s_cum[k] <= u0 < s_cum[k + 1]
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (s_cum[mid] <= u0)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
+    while (s_cum[lo + 1] <= u0) ++lo;
     const int u = u0 + lane;
     if (u >= total) continue;
     int k = lo;
@@ -726,21 +755,30 @@ __device__ __forceinline__ void reg_phase(const void* in, int64_t base, int n, i
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int G = merge_groups(p);
-  int col[kChunk];
+  uint32_t col[kChunk];
 #pragma unroll
-  for (int e = 0; e < kChunk; ++e) col[e] = (lane * kChunk + e) % p;
+  for (int e = 0; e < kChunk; ++e) col[e] = (uint32_t)(lane * kChunk + e) % (uint32_t)p;
   const int nodes = 1 << d_r;
   for (int b = wave; b < nodes; b += WV) {
     int r0b, nb;
     node_geometry(n, d_r, b, r0b, nb);
     if (nb == 0) continue;
-    float v[kRegRows][kChunk];
+    uint32_t raw[kRegRows][kChunk];
     const int64_t rb = base + (int64_t)r0b * p;
 #pragma unroll
     for (int r = 0; r < kRegRows; ++r)
 #pragma unroll
       for (int e = 0; e < kChunk; ++e)
-        v[r][e] = r < nb ? load_sample(in, DT, rb + (int64_t)r * p + col[e]) : 0.0f;
+        // 16-bit types: unconditional loads (rows past the node re-read its
+        // last row), so that the conversions are not sunk between them; the
+        // row start is uniform and the lane's column a 32-bit offset
+        raw[r][e] = DT == FFA_F32 ? (r < nb ? load_row_bits<DT>(in, rb + (int64_t)r * p, col[e]) : 0u)
+                                  : load_row_bits<DT>(in, rb + (int64_t)(r < nb ? r : nb - 1) * p, col[e]);
+    float v[kRegRows][kChunk];
+#pragma unroll
+    for (int r = 0; r < kRegRows; ++r)
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) v[r][e] = r < nb ? bits_value<DT>(raw[r][e]) : 0.0f;
     switch (nb) {
       case 2: RegFFA<0, 2>::run(v); break;
       case 3: RegFFA<0, 3>::run(v); break;
@@ -832,17 +870,23 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
   if (JS == 1) {
     constexpr int KC = 5;  // 5 x 64 columns >= p + kHalo whenever one group per lane suffices
-    float v[kStageMax][KC];
+    if (nrw == 0) return;
+    // 16-bit types: unconditional loads (rows past the wave's count re-read
+    // its first row, columns past the copy wrap), so the conversions are not
+    // sunk between them; FP32 keeps the conditions
+    uint32_t v[kStageMax][KC];
 #pragma unroll
     for (int r = 0; r < kStageMax; ++r) {
-      const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
-                        ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
+      const int rr = (DT == FFA_F32 || r < nrw) ? r : 0;
+      const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, rr) |
+                        ((int64_t)__builtin_amdgcn_readlane(hi, rr) << 32);
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
         int col = c < p ? c : c - p;
         if (col >= p) col %= p;  // rows shorter than the copy
-        v[r][k] = (r < nrw && c < width) ? load_sample(base, DT, g + col) : 0.0f;
+        v[r][k] = DT == FFA_F32 ? ((r < nrw && c < width) ? load_bits<DT>(base, g + col) : 0u)
+                                : load_bits<DT>(base, g + col);
       }
     }
 #pragma unroll
@@ -850,7 +894,7 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
-        if (r < nrw && c < width) rows[(wave + WV * r) * stride + c] = v[r][k];
+        if (r < nrw && c < width) rows[(wave + WV * r) * stride + c] = bits_value<DT>(v[r][k]);
       }
     return;
   }
@@ -861,7 +905,7 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
       g[u] = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, min(rb + u, 63)) |
              ((int64_t)__builtin_amdgcn_readlane(hi, min(rb + u, 63)) << 32);
     for (int c0 = 0; c0 < width; c0 += 128) {
-      float v[4][2];
+      uint32_t v[4][2];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -869,14 +913,15 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
           const int c = c0 + lane + 64 * k;
           int col = c < p ? c : c - p;
           if (col >= p) col %= p;
-          v[u][k] = (rb + u < nrw && c < width) ? load_sample(base, DT, g[u] + col) : 0.0f;
+          v[u][k] = (rb + u < nrw && c < width) ? load_bits<DT>(base, g[u] + col) : 0u;
         }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
-          if (rb + u < nrw && c < width) rows[(wave + WV * (rb + u)) * stride + c] = v[u][k];
+          if (rb + u < nrw && c < width)
+            rows[(wave + WV * (rb + u)) * stride + c] = bits_value<DT>(v[u][k]);
         }
     }
   }
@@ -903,7 +948,7 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
       const int c = lane + 64 * k;
       int col = c < p ? c : c - p;
       if (col >= p) col %= p;
-      v[r][k] = (r < nrw && c < width) ? base[g + col] : 0.0f;
+      v[r][k] = (r < nrw && c < width) ? bits_value<FFA_F32>(load_bits<FFA_F32>(base, g + col)) : 0.0f;
     }
   }
   work();
