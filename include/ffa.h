@@ -63,8 +63,9 @@ typedef struct ffa_ctx ffa_ctx;
  *                deviation of the whole series, both computed in FP64 on the
  *                device (Sec. 5.2); 0: the series is used as given (it should
  *                then have zero mean and unit variance).
- *   dtype        ffa_dtype of the series. The downsampled series is stored
- *                in the same type; folding and S/N accumulate in FP32. */
+ *   dtype        ffa_dtype of the series. The statistics and the
+ *                downsampler read it in this type; the downsampled series
+ *                and everything after it are FP32. */
 typedef struct {
   double tsamp;
   double period_min;

@@ -58,7 +58,6 @@ struct DevBuf {
   }
 };
 
-size_t dtype_bytes(int dt) { return dt == FFA_F32 ? 4 : 2; }
 
 // Key of a plan: every parameter that changes it.
 std::string plan_key(const ffa_search_params& a, int64_t nsamp) {
@@ -342,7 +341,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
 // Grows the context workspace for a job. Captured graphs hold the old
 // addresses, so they are dropped whenever a buffer moves.
 ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
-  const size_t db = dtype_bytes(job.dtype);
+  const size_t db = 4;  // downsampled series: FP32 whatever the input's storage
   DevBuf* bufs[] = {&ctx->ds_buf, &ctx->scr0, &ctx->scr1, &ctx->stats, &ctx->norm,
                     &ctx->partials, &ctx->flag, &ctx->counters, &ctx->ticket};
   const size_t want[] = {(size_t)job.ds_total * db + 16,
@@ -418,7 +417,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   {
   TimedScope ts(ctx, 1, stream, timed);
   HIP_TRY(ctx, launch_downsample(sd, job.nseries, job.oct.as<OctaveDev>(), ctx->norm.as<float>(),
-                                 job.dtype, ctx->ds_buf.ptr, job.dtype, job.ds_blocks,
+                                 job.dtype, ctx->ds_buf.ptr, FFA_F32, job.ds_blocks,
                                  job.ds_lds_floats, stream),
           "downsample kernel");
   }
@@ -427,7 +426,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   pa.waves = job.tiling.waves;
   pa.xf = job.xf.as<XformDesc>();
   pa.in = ctx->ds_buf.ptr;
-  pa.in_dtype = job.dtype;
+  pa.in_dtype = FFA_F32;
   pa.num_widths = job.num_widths;
   pa.scr0 = ctx->scr0.as<float>();
   pa.scr1 = ctx->scr1.as<float>();

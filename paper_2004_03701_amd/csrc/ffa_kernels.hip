@@ -315,7 +315,7 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 constexpr int kDsMaxOctaves = 128;
 constexpr int kDsLoadIters = 24;  // samples a thread loads before storing (block + halo <= 24 * 512)
 
-template <int DT>
+template <int DT, int DO>
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
                                                            int32_t nseries,
                                                            const OctaveDev* oct,
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
     float y = (1.0f - fa) * xs[ia] + (ps[ib] - ps[ia + 1]);
     if ((uint32_t)b != 0u) y += fb * xs[ib];
-    store_sample(out, DT, s_off[k] + j, y * inv);
+    store_sample(out, DO, s_off[k] + j, y * inv);
   }
 }
 
@@ -1751,33 +1751,40 @@ int32_t downsample_block_samples(int32_t max_halo) {
   return b;
 }
 
-template <int DT>
+template <int DT, int DO>
 hipError_t launch_downsample_t(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
                                const float* norm, void* out, int64_t nblocks, size_t lds,
                                hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample<DT>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample<DT, DO>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kLdsBytes - 4096);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_downsample<DT>, dim3((unsigned)nblocks), dim3(kDsThreads), lds, stream,
-                     series_dev, nseries, oct, norm, out);
+  hipLaunchKernelGGL((k_downsample<DT, DO>), dim3((unsigned)nblocks), dim3(kDsThreads), lds,
+                     stream, series_dev, nseries, oct, norm, out);
   return hipGetLastError();
 }
 
+// Output in the input's type, or FP32 from any input.
 hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
                              const float* norm, int32_t dtype, void* out, int32_t out_dtype,
                              int64_t nblocks, int32_t lds_floats, hipStream_t stream) {
   const size_t lds = (size_t)lds_floats * sizeof(float);
-  if (lds > (size_t)(kLdsBytes - 4096) || out_dtype != dtype) return hipErrorInvalidValue;
+  if (lds > (size_t)(kLdsBytes - 4096) || (out_dtype != dtype && out_dtype != FFA_F32))
+    return hipErrorInvalidValue;
+  const auto* s = series_dev;
   if (dtype == FFA_BF16)
-    return launch_downsample_t<FFA_BF16>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
+    return out_dtype == FFA_F32
+               ? launch_downsample_t<FFA_BF16, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream)
+               : launch_downsample_t<FFA_BF16, FFA_BF16>(s, nseries, oct, norm, out, nblocks, lds, stream);
   if (dtype == FFA_F16)
-    return launch_downsample_t<FFA_F16>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
-  return launch_downsample_t<FFA_F32>(series_dev, nseries, oct, norm, out, nblocks, lds, stream);
+    return out_dtype == FFA_F32
+               ? launch_downsample_t<FFA_F16, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream)
+               : launch_downsample_t<FFA_F16, FFA_F16>(s, nseries, oct, norm, out, nblocks, lds, stream);
+  return launch_downsample_t<FFA_F32, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream);
 }
 
 int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
@@ -1824,10 +1831,10 @@ hipError_t dispatch(const PassArgs& args, int grid, hipStream_t stream) {
   const bool big = args.waves == kWavesLarge;
 #define FFA_LAUNCH(WV, JS, DT) \
   (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream) : launch_pass_t<WV, JS, DT>(args, stream))
-#define FFA_BY_DT(WV, JS)                                                              \
-  (args.in_dtype == FFA_BF16 ? FFA_LAUNCH(WV, JS, FFA_BF16)                          \
-                             : (args.in_dtype == FFA_F16 ? FFA_LAUNCH(WV, JS, FFA_F16) \
-                                                         : FFA_LAUNCH(WV, JS, FFA_F32)))
+// the folded series are FP32 (the downsampler writes FP32 whatever the
+// input's storage type)
+#define FFA_BY_DT(WV, JS) \
+  (args.in_dtype == FFA_F32 ? FFA_LAUNCH(WV, JS, FFA_F32) : hipErrorInvalidValue)
   if (big) return j1 ? FFA_BY_DT(kWavesLarge, 1) : FFA_BY_DT(kWavesLarge, 0);
   return j1 ? FFA_BY_DT(kWavesSmall, 1) : FFA_BY_DT(kWavesSmall, 0);
 #undef FFA_BY_DT
