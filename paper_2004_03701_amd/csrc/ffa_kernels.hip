@@ -1660,13 +1660,24 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     snr_general<WV>(a, rows, stride, p, nvalid, snrbuf, scale, out);
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup i runs on XCD i mod
+// 8), each XCD with its own L2. This maps them so that each XCD takes one
+// contiguous eighth of the tile list (neighbouring tiles read neighbouring
+// rows of the same octave), a bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  constexpr int kXcds = 8;
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = bid % kXcds, k = bid / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // One instantiation per (column groups per lane, input storage type): JS = 1
 // needs every tile's p <= 316 (one group per lane); JS = 0 serves any p.
 template <int WV, int JS, int DT>
 // Four waves per SIMD: two 8-wave workgroups (or one of 16) per CU, 128 VGPRs.
 __global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_ffa_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const TileDesc t = a.tiles[blockIdx.x];
+  const TileDesc t = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const XformDesc x = a.xf[t.xf];
   ffa_tile<WV, JS, DT>(a, t, x, smem);
 }
