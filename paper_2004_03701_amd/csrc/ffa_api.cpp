@@ -227,7 +227,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     sd[i].halo = (int32_t)(pl.ds_fx_max >> 32) + 2;
     sd[i].block = downsample_block_samples(sd[i].halo);
     sd[i].pad = 0;
-    job->ds_lds_floats = std::max<int32_t>(job->ds_lds_floats, 2 * (sd[i].block + sd[i].halo) + 2);
+    job->ds_lds_floats = std::max<int32_t>(job->ds_lds_floats, downsample_lds_floats(sd[i].block, sd[i].halo));
     if (a.normalise) job->any_normalise = true;
     chunk += (nsamp[i] + sd[i].block - 1) / sd[i].block;
     for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
@@ -794,7 +794,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
     HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
   const int64_t nblocks = (nsamp + bs - 1) / bs;
   HIP_TRY(ctx, launch_downsample(t1.as<SeriesDev>(), 1, t2.as<OctaveDev>(), ctx->norm.as<float>(),
-                                 dtype, out_dev, dtype, nblocks, 2 * (bs + halo) + 2, st),
+                                 dtype, out_dev, dtype, nblocks, downsample_lds_floats(bs, halo), st),
           "downsample kernel");
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
   return FFA_OK;

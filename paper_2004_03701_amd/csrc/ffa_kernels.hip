@@ -294,10 +294,11 @@ __global__ void k_norm_from_stats(const double* stats, float* norm) {
 // Downsampling (Sec. 5.3, App. A.4). Output j of octave k integrates the
 // normalised series over [j ds, (j+1) ds), ds = ds_fx / 2^32, each input
 // sample weighted by its overlap with the window. A block stages a stretch
-// of the raw series in LDS once and emits every output of every octave whose
-// window starts in it, using an exclusive prefix sum over the stretch:
-//   y = (1 - fa) x[ia] + (P[ib] - P[ia + 1]) + fb x[ib]
-// with a = ia + fa and b = ib + fb the window edges.
+// of the raw series in LDS once, turns it in place into its exclusive prefix
+// sum P, and emits every output of every octave whose window starts in it:
+//   y = (1 - fa) x[ia] + (P[ib] - P[ia + 1]) + fb x[ib],  x[i] = P[i + 1] - P[i]
+// with a = ia + fa and b = ib + fb the window edges. Only P is kept (half the
+// LDS of keeping x too, so four blocks fit a CU).
 // ---------------------------------------------------------------------------
 
 constexpr int kDsThreads = 512;
@@ -314,6 +315,8 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 
 constexpr int kDsMaxOctaves = 128;
 constexpr int kDsLoadIters = 24;  // samples a thread loads before storing (block + halo <= 24 * 512)
+constexpr int kDsSegMax = kDsLoadIters + 1;  // longest prefix segment of a thread (odd)
+
 
 template <int DT, int DO>
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
@@ -348,8 +351,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   const int64_t c1 = min(c0 + (int64_t)sd.block, sd.nsamp);
   const int64_t cend = min(sd.nsamp, c1 + (int64_t)sd.halo);
   const int len = (int)(cend - c0);
-  float* xs = sm;                 // len samples
-  float* ps = sm + len + 1;       // len + 1 prefix sums
+  float* ps = sm;  // len samples, then in place their len + 1 exclusive prefix sums
   const float mean = sd.normalise ? norm[2 * si] : 0.0f;
   const float inv = sd.normalise ? norm[2 * si + 1] : 1.0f;
   // every load of a thread is in flight before its first LDS store
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
 #pragma unroll
     for (int k = 0; k < kDsLoadIters; ++k) {
       const int q = q0 + tid + k * kDsThreads;
-      if (q < len) xs[q] = bits_value<DT>(v[k]) - mean;
+      if (q < len) ps[q] = bits_value<DT>(v[k]) - mean;
     }
   }
   // window ranges of every octave, one octave per thread: outputs whose
@@ -398,21 +400,41 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     if (lane == 0) s_cum[0] = 0;
   }
   __syncthreads();
-  // exclusive prefix: contiguous segments per thread (an odd length, so the
-  // lanes' reads fall in distinct banks), then a block scan
+  // exclusive prefix, in place: each thread holds a contiguous segment of an
+  // odd length (the lanes' reads fall in distinct banks) in registers, then a
+  // block scan of the segment sums
   const int seg = ((len + kDsThreads - 1) / kDsThreads) | 1;
   const int q0 = min(tid * seg, len), q1 = min(q0 + seg, len);
+  const bool in_regs = seg <= kDsSegMax;  // the same in every thread
+  float xv[kDsSegMax];
   float run = 0.0f;
-  for (int q = q0; q < q1; ++q) run += xs[q];
+  if (in_regs) {
+#pragma unroll
+    for (int k = 0; k < kDsSegMax; ++k) {
+      xv[k] = q0 + k < q1 ? ps[q0 + k] : 0.0f;
+      run += xv[k];
+    }
+  } else {  // long blocks (very large factors): two passes over LDS
+    for (int q = q0; q < q1; ++q) run += ps[q];
+  }
   float incl = wave_scan_dpp_f32(run);
   if (lane == 63) s_part[wave] = incl;
   __syncthreads();
   float woff = 0.0f;
   for (int w = 0; w < wave; ++w) woff += s_part[w];
   float acc = woff + incl - run;
-  for (int q = q0; q < q1; ++q) {
-    ps[q] = acc;
-    acc += xs[q];
+  if (in_regs) {
+#pragma unroll
+    for (int k = 0; k < kDsSegMax; ++k) {
+      if (q0 + k < q1) ps[q0 + k] = acc;
+      acc += xv[k];
+    }
+  } else {
+    for (int q = q0; q < q1; ++q) {  // each thread rewrites only its own segment
+      const float x = ps[q];
+      ps[q] = acc;
+      acc += x;
+    }
   }
   if (q1 == len && q0 < q1) ps[len] = acc;
   if (len == 0 && tid == 0) ps[0] = 0.0f;
@@ -434,8 +456,9 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
     const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
     const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
-    float y = (1.0f - fa) * xs[ia] + (ps[ib] - ps[ia + 1]);
-    if ((uint32_t)b != 0u) y += fb * xs[ib];
+    const float pa0 = ps[ia], pa1 = ps[ia + 1], pb0 = ps[ib];
+    float y = (1.0f - fa) * (pa1 - pa0) + (pb0 - pa1);
+    if ((uint32_t)b != 0u) y += fb * (ps[ib + 1] - pb0);
     store_sample(out, DO, s_off[k] + j, y * inv);
   }
 }
@@ -1755,6 +1778,8 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
                      blocks_per_series, partials, stats, norm, flag);
   return hipGetLastError();
 }
+
+int32_t downsample_lds_floats(int32_t block, int32_t halo) { return block + halo + 2; }
 
 int32_t downsample_block_samples(int32_t max_halo) {
   int32_t b = 8192;

@@ -99,7 +99,7 @@ def test_series_stats(ctx):
     assert abs(st[1] - sd) < 1e-11 * sd
 
 
-@pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3])
+@pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3, 5000.3])
 def test_downsample(ctx, ds):
     n = 300_001
     x = (np.random.default_rng(5).standard_normal(n) + 0.3).astype(np.float32)
