@@ -135,6 +135,28 @@ def test_search_small_multi_octave(ctx):
     assert snr_close(snr, ref.snr) < SNR_RTOL
 
 
+# Each S/N form against the oracle: the compiled width grids in their
+# register-window form (p large enough), in their ring form (short rows), and
+# general widths; with a pulse so that the maxima are not all noise.
+@pytest.mark.parametrize("widths,bmin,bmax,pmin", [
+    ((1, 2, 3, 4, 6, 9, 13, 19, 28), 40, 47, 40.0),     # paper grid, ring form
+    ((1, 2, 3, 4, 6, 9, 13, 19, 28), 96, 103, 96.0),    # paper grid, register windows
+    ((1, 2, 3, 5, 8, 12, 19, 30, 48), 60, 67, 60.0),    # duty grid, ring form
+    ((1, 2, 3, 5, 8, 12, 19, 30, 48), 120, 127, 120.0),  # duty grid, register windows
+    ((1, 2, 5, 7, 11), 100, 107, 100.0),                 # general widths
+])
+def test_snr_forms_match_oracle(ctx, widths, bmin, bmax, pmin):
+    g = synth.rng(11, bmin)
+    x = synth.inject(synth.noise(60_000, g),
+                     synth.Pulse(period=pmin * 1.37, duty=0.05, amplitude=12.0, phi0=0.3))
+    cfg = synth.SearchConfig(1.0, pmin, pmin * 4.0, bmin, bmax, widths)
+    per, bins, snr = run_search(ctx, x, cfg)
+    ref = oracle.search(x, 1.0, pmin, pmin * 4.0, bmin, bmax, widths)
+    assert np.array_equal(per, ref.periods) and np.array_equal(bins, ref.bins)
+    assert snr_close(snr, ref.snr) < SNR_RTOL
+    assert float(np.max(ref.snr)) > 8.0  # the pulse is found
+
+
 def test_search_integer_series_matches_closely(ctx):
     # integer samples, ds = 1, no normalisation: boxcar sums are exact
     x = np.random.default_rng(8).integers(-8, 9, size=40_000).astype(np.float32)
