@@ -22,6 +22,11 @@ constexpr int kMaxFullLevels = 8;  // ceil(log2(kMaxFullRows))
 // (cross-lane shifts by one lane); log2 of it is the most register levels.
 constexpr int kRegRows = 8;
 constexpr int kRegLevels = 3;
+// Most LDS merge levels of a full tile above its register levels (tiles of
+// at most 128 rows: nodes of at most 8 rows at depth 4).
+constexpr int kMaxTileLevels = 4;
+static_assert(kWavesLarge * kStageMax <= (kRegRows << kMaxTileLevels),
+              "a full tile's LDS levels fit kMaxTileLevels");
 // Largest number of boxcar widths and of bins per profile.
 constexpr int kMaxWidths = 32;
 constexpr int kMaxBins = 1280;

@@ -836,6 +836,23 @@ __device__ __forceinline__ void full_tile_pairs(const PassArgs& a, int64_t base,
   const int G = merge_groups(p);
   int d_r = 0;
   while (((n + (1 << d_r) - 1) >> d_r) > kRegRows) ++d_r;
+  // the lane's pair operations of every LDS level, fetched before the
+  // register levels so that their latency hides behind them
+  const int32_t* offs = a.full_pops_off + n * (kMaxFullLevels + 1);
+  uint32_t w0[kMaxTileLevels], w1[kMaxTileLevels];
+#pragma unroll
+  for (int lev = 0; lev < kMaxTileLevels; ++lev) {
+    w0[lev] = 0;
+    w1[lev] = 1u << 31;  // no operation
+    if (lev < d_r) {
+      const int o0 = offs[lev], cnt = offs[lev + 1] - o0;
+      const int q = wave + WV * lane;
+      if (q < cnt) {
+        w0[lev] = a.full_pops[2 * (o0 + q)];
+        w1[lev] = a.full_pops[2 * (o0 + q) + 1];
+      }
+    }
+  }
   reg_phase<WV, DT>(a.in, base, n, p, d_r, rows, stride);
   if (d_r == 0) {
     __syncthreads();
@@ -846,25 +863,29 @@ __device__ __forceinline__ void full_tile_pairs(const PassArgs& a, int64_t base,
   // values written to the same place)
   const int lane20 = (lane < G ? lane : lane % G) * kChunk * 4;
   const int junk4 = (R + 1) * stride4;
-  const int32_t* offs = a.full_pops_off + n * (kMaxFullLevels + 1);
-  auto fetch = [&](int lev) {
+  auto decode = [&](uint32_t x0, uint32_t x1) {
     PairOp op{0, 0, 0, 0, junk4, junk4};
-    if (lev >= 0) {
-      const int o0 = offs[lev], cnt = offs[lev + 1] - o0;
-      const int q = wave + WV * lane;
-      if (q < cnt) {
-        const uint32_t w0 = a.full_pops[2 * (o0 + q)], w1 = a.full_pops[2 * (o0 + q) + 1];
-        op.oa = (int)(w0 & 255u) * stride4;
-        op.ha = (int)((w0 >> 8) & 255u) * stride4;
-        op.hb = (int)((w0 >> 16) & 255u) * stride4;
-        op.t = (int)(w0 >> 24) * stride4;
-        int rot = (int)(w1 & 0xffffu);
-        if (rot >= p) rot %= p;
-        op.rot4 = rot * 4;
-        op.ob = (w1 >> 16) & 1u ? junk4 : op.oa + stride4;
-      }
+    if (!(x1 >> 31)) {
+      op.oa = (int)(x0 & 255u) * stride4;
+      op.ha = (int)((x0 >> 8) & 255u) * stride4;
+      op.hb = (int)((x0 >> 16) & 255u) * stride4;
+      op.t = (int)(x0 >> 24) * stride4;
+      int rot = (int)(x1 & 0xffffu);
+      if (rot >= p) rot %= p;
+      op.rot4 = rot * 4;
+      op.ob = (x1 >> 16) & 1u ? junk4 : op.oa + stride4;
     }
     return op;
+  };
+  auto fetch = [&](int lev) {
+    uint32_t x0 = 0, x1 = 1u << 31;
+#pragma unroll
+    for (int k = 0; k < kMaxTileLevels; ++k)
+      if (k == lev) {
+        x0 = w0[k];
+        x1 = w1[k];
+      }
+    return decode(x0, x1);
   };
   int lev = d_r - 1;
   PairOp cur = fetch(lev);
