@@ -165,7 +165,7 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);
 
 /* Tile shapes and scheduling of the search kernels. lds_rows: rows of a
  * profile tile held in LDS (0 = the largest that fits); levels_per_pass:
- * merge levels per pass above the bottom subtrees (1..4); persistent: 1 runs
+ * merge levels per pass above the bottom subtrees (1..5); persistent: 1 runs
  * all passes of a group of series in one persistent launch (tiles taken in
  * ticket order, later passes waiting on per-transform completion counters),
  * 0 launches one kernel per pass; waves_per_group: 16 (one workgroup per CU
@@ -181,7 +181,7 @@ typedef struct {
 ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out);
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* tiling);
 
-/* Times candidate tilings (8 or 16 waves per workgroup, 2, 3 or 4 levels per
+/* Times candidate tilings (8 or 16 waves per workgroup, 3, 4 or 5 levels per
  * pass, per-pass or persistent launches) on a representative batch (same
  * arguments as ffa_search_batch; outputs go to a context-owned buffer) with
  * HIP events on `stream`, keeps the fastest in the context and, if cache_path

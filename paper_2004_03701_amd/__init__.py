@@ -281,7 +281,7 @@ def ffa_get_tiling(ctx) -> ffa_tiling:
     return t
 
 
-def ffa_set_tiling(ctx, lds_rows: int = 0, levels_per_pass: int = 4,
+def ffa_set_tiling(ctx, lds_rows: int = 0, levels_per_pass: int = 5,
                    persistent: bool = False, waves_per_group: int = 8) -> None:
     t = ffa_tiling(lds_rows, levels_per_pass, 1 if persistent else 0, waves_per_group)
     _check(lib().ffa_set_tiling(ctx, ctypes.byref(t)), ctx)

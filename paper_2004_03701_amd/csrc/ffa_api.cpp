@@ -829,7 +829,7 @@ ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* t) {
       t->levels_per_pass > kMaxRangeLevels || (t->persistent != 0 && t->persistent != 1) ||
       (t->waves_per_group != kWavesLarge && t->waves_per_group != kWavesSmall))
     return fail(ctx, FFA_ERR_INVALID_ARG,
-                "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 4, persistent 0 or 1, "
+                "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 5, persistent 0 or 1, "
                 "waves_per_group 8 or 16");
   ctx->tiling.lds_rows = t->lds_rows;
   ctx->tiling.levels_per_pass = t->levels_per_pass;
@@ -942,7 +942,7 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
   const bool timing = ctx->timing;
   ctx->timing = false;
   for (int waves : {kWavesSmall, kWavesLarge})
-    for (int levels : {2, 3, 4})
+    for (int levels : {3, 4, 5})
       for (int persistent : {0, 1}) {
         Tiling t;
         t.waves = waves;

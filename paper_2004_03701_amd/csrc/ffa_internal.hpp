@@ -32,7 +32,7 @@ constexpr int kMaxWidths = 32;
 constexpr int kMaxBins = 1280;
 constexpr int kSnrColsMax = (kMaxBins + 63) / 64;  // phases per lane, general S/N path
 // Largest number of merge levels in one range pass (2^L source nodes).
-constexpr int kMaxRangeLevels = 4;
+constexpr int kMaxRangeLevels = 5;
 constexpr int kMetaNodes = (2 << kMaxRangeLevels) - 1;
 // Range-tile metadata in LDS: six arrays over the nodes, one over the levels.
 constexpr int kMetaInts = 6 * kMetaNodes + kMaxRangeLevels + 4;

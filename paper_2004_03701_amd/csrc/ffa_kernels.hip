@@ -1237,11 +1237,13 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
   const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
   const int q_lane = wave + WV * lane;
   // the source rows' loads are in flight while the pair operations of every
-  // level are built: kThreads / kMaxRangeLevels threads per level, an equal
-  // share of them per node of the level
+  // level are built: kThreads / 8 threads per level (a power of two, at least
+  // one per node), an equal share of them per node of the level
   load_rows_overlap<WV>(rows, total, p, stride, src + x.scr_off,
                         q_lane < total ? (int64_t)th[q_lane] * p : 0, [&]() {
-  constexpr int kPerLevel = kThreads / kMaxRangeLevels;
+  static_assert(kMaxRangeLevels <= 8 && (kThreads / 8) >> (kMaxRangeLevels - 1) >= 1,
+                "thread shares of the pair operations");
+  constexpr int kPerLevel = kThreads / 8;
   const int l = tid / kPerLevel;
   if (l < L) {
     const int slots = kPerLevel >> l;

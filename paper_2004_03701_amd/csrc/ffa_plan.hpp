@@ -51,7 +51,7 @@ double trial_period(int64_t s, int64_t m, int64_t p, double tau);
 // Tile shapes.
 struct Tiling {
   int32_t lds_rows = 0;         // 0: the largest that fits
-  int32_t levels_per_pass = 4;  // 1..kMaxRangeLevels
+  int32_t levels_per_pass = 5;  // 1..kMaxRangeLevels
   int32_t persistent = 0;       // 1: one persistent launch per group of series
   int32_t waves = kWavesSmall;  // waves per workgroup: 16 (one per CU) or 8 (two per CU)
 };
