@@ -296,6 +296,61 @@ def test_low_precision_storage(ctx, dt, tdt, bound):
     assert err_dq.max() < bound * 8
 
 
+# Workload 3 at full size (2^23 samples at 64 us) in the batch call with the
+# default tiling (the configuration the benchmark times): every periodogram row
+# of four series (two with a pulse) against the oracle in FP32; then the same
+# series normalised in FP64 and stored as BF16 and as FP16 (workload 4): S/N
+# error against the oracle on the FP32 series and detection agreement at
+# S/N >= 7, per (row, width) and per injected pulse.
+def test_workload3_full_size_batch_and_low_precision(ctx):
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    idx = [int(pulsed[0]), int(pulsed[1]), 1, 3]
+    xs, pulses = zip(*[synth.workload3_series(i, pulsed=pulsed) for i in idx])
+    refs = [oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                          cfg.bins_max, cfg.widths) for x in xs]
+    ref_all = np.concatenate([r.snr for r in refs])
+
+    def run(arrs, dt):
+        series = [dev(a) if dt == ffa.FFA_F32 else a for a in arrs]
+        prm = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                               cfg.bins_max, cfg.widths, dtype=dt) for _ in arrs]
+        snr, _ = ffa.ffa_search_batch(ctx, series, prm)
+        torch.cuda.synchronize()
+        assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+        return snr.cpu().numpy().astype(np.float64)
+
+    snr32 = run(xs, ffa.FFA_F32)
+    assert snr32.shape == ref_all.shape
+    assert snr_close(snr32, ref_all) < SNR_RTOL
+    rows = [r.snr.shape[0] for r in refs]
+    starts = np.cumsum([0] + rows)
+    for tdt, dt, bound_max, bound_med in ((torch.bfloat16, ffa.FFA_BF16, 0.1, 0.01),
+                                          (torch.float16, ffa.FFA_F16, 0.01, 1e-3)):
+        lowp = []
+        for x in xs:
+            xd = x.astype(np.float64)
+            xn = (xd - xd.mean()) / np.sqrt(((xd - xd.mean()) ** 2).mean())
+            lowp.append(torch.from_numpy(xn.astype(np.float32)).to(tdt).cuda())
+        snr = run(lowp, dt)
+        err = np.abs(snr - ref_all)
+        det_g, det_r = snr >= 7.0, ref_all >= 7.0
+        agree = float(np.mean(det_g == det_r))
+        found = []
+        for k, (pu, r) in enumerate(zip(pulses, refs)):
+            if pu is None:
+                continue
+            period_s = pu.period * cfg.tsamp
+            near = np.abs(r.periods / period_s - 1.0) < 0.02
+            blk = snr[starts[k]:starts[k + 1]]
+            found.append((bool(blk[near].max() >= 7.0), bool(r.snr[near].max() >= 7.0)))
+        print(f"{tdt}: max |dS/N| {err.max():.3e} median {np.median(err):.3e}; "
+              f"detections (S/N >= 7) gpu {int(det_g.sum())} oracle {int(det_r.sum())}, "
+              f"agreement per (row, width) {agree:.6f}; pulses found gpu/oracle {found}")
+        assert err.max() < bound_max and np.median(err) < bound_med
+        assert all(a == b for a, b in found)
+
+
 def test_persistent_launch_equals_pass_launches(ctx):
     # same tiles either way: the periodograms are bit-identical
     xs, cfgs = batch_inputs(5)
