@@ -11,6 +11,10 @@ pulse; periods 0.5-10 s, 240-259 bins, 9 boxcar widths (1..48 bins). It is
 run with the series stored as bfloat16 (normalised in FP64 beforehand), the
 headline, and as plain float32 for comparison.
 
+Each variant is timed twice over the same steps: with eager launches, each
+bracketed by HIP events (the per-kernel times behind the roofline), and as
+replays of the step captured in one hipGraph (the headline value).
+
 Prints one JSON line (rank 0).
 """
 import argparse
@@ -37,7 +41,9 @@ def parse():
     ap.add_argument("--series", type=int, default=512)
     ap.add_argument("--log2n", type=int, default=23)
     ap.add_argument("--variants", default="bf16,f32,f16")
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: after the per-kernel timed steps, time the same steps again as "
+                         "hipGraph replays (the headline value); 0: eager launches only")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="batch", choices=["batch", "uneven"])
@@ -223,20 +229,35 @@ def main():
                       "persistent": t.persistent, "lds_rows": t.lds_rows}
             log(f"variant {v}: autotuned on {k} series -> {tiling}")
         for _ in range(a.warmup):
-            ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
+            ffa.ffa_search_batch(ctx, series, prm, snr=snr)
         torch.cuda.synchronize()
-        log(f"variant {v}: warm-up done, timing {a.steps} steps")
-        ffa.ffa_set_timing(ctx, not a.graph)
+        log(f"variant {v}: warm-up done, timing {a.steps} steps (per-kernel HIP events)")
+        # eager launches, each bracketed by HIP events on its stream
+        ffa.ffa_set_timing(ctx, True)
         ffa.ffa_read_timing(ctx, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(a.steps):
-            ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=bool(a.graph))
+            ffa.ffa_search_batch(ctx, series, prm, snr=snr)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        wall_eager = time.perf_counter() - t0
         tm = ffa.ffa_read_timing(ctx, reset=True)
         ffa.ffa_set_timing(ctx, False)
         assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+        wall = wall_eager
+        graph_ms = None
+        if a.graph:
+            # the same steps as replays of one captured hipGraph
+            ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=True)  # capture
+            torch.cuda.synchronize()
+            log(f"variant {v}: timing {a.steps} graph replays")
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                ffa.ffa_search_batch(ctx, series, prm, snr=snr, use_graph=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            graph_ms = 1e3 * wall / a.steps
+            assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
         ffa.ffa_set_tiling(ctx)
         ms = 1e3 * wall / a.steps
         profiles = rows1 * a.series
@@ -245,7 +266,8 @@ def main():
         fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
         res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),
                "profiles": profiles, "alg_bytes_fold": alg_bytes, "timing": tm,
-               "tiling": tiling}
+               "tiling": tiling, "eager_ms_per_step": 1e3 * wall_eager / a.steps,
+               "graph_ms_per_step": graph_ms}
         if fold_ms:
             res["fold_ms_per_step"] = fold_ms
             res["fold_launches_per_step"] = tm["fold_launches"] / a.steps

@@ -632,8 +632,8 @@ __device__ __forceinline__ void merge_level(float* rows, int count, int p, int s
 // row (rotations k and k + 1), one lane reads kChunk + 1 bins of the tail
 // once and the head row(s), and writes both outputs: 15 LDS instructions and
 // about 24 VALU instructions per 10 outputs instead of 18 and 35 for two
-// single rows. A single (a row with no partner) writes its second output to
-// the junk row. Operation q of a level is held by lane q / WV of wave q % WV
+// single rows. A single (a row with no partner) has no second output
+// (ob = -1). Operation q of a level is held by lane q / WV of wave q % WV
 // as LDS byte offsets.
 // ---------------------------------------------------------------------------
 
@@ -681,11 +681,13 @@ __device__ __forceinline__ void merge_pairs_ns(unsigned char* base, int p4, int 
       const int oa = __builtin_amdgcn_readlane(op.oa, r);
       const int ob = __builtin_amdgcn_readlane(op.ob, r);
       float* wa = reinterpret_cast<float*>(base + oa + lane20);
-      float* wb = reinterpret_cast<float*>(base + ob + lane20);
 #pragma unroll
       for (int e = 0; e < kChunk; ++e) wa[e] = a[r][e];
+      if (ob >= 0) {  // not a single
+        float* wb = reinterpret_cast<float*>(base + ob + lane20);
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e) wb[e] = b[r][e];
+        for (int e = 0; e < kChunk; ++e) wb[e] = b[r][e];
+      }
     }
   }
   __syncthreads();
@@ -873,7 +875,7 @@ __device__ __forceinline__ void full_tile_pairs(const PassArgs& a, int64_t base,
       int rot = (int)(x1 & 0xffffu);
       if (rot >= p) rot %= p;
       op.rot4 = rot * 4;
-      op.ob = (x1 >> 16) & 1u ? junk4 : op.oa + stride4;
+      op.ob = (x1 >> 16) & 1u ? -1 : op.oa + stride4;
     }
     return op;
   };
@@ -1262,7 +1264,7 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
         e[2] = zero4;
         e[3] = 0;
         e[4] = hoff * stride4;
-        e[5] = junk4;
+        e[5] = -1;
         continue;
       }
       int s;
@@ -1286,7 +1288,7 @@ __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDe
       e[2] = (tc_off + (j - tc_lo)) * stride4;
       e[3] = rot * 4;
       e[4] = oa * stride4;
-      e[5] = single ? junk4 : (oa + 1) * stride4;
+      e[5] = single ? -1 : (oa + 1) * stride4;
     }
   }
   });
