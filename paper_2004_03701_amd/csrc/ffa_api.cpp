@@ -34,7 +34,10 @@ struct DevBuf {
   ~DevBuf() {
     if (ptr) (void)hipFree(ptr);
   }
-  hipError_t reserve(size_t n) {
+  // Grows to at least n bytes (contents are not kept); `zero` clears a new
+  // allocation (never called inside a graph capture: every buffer is
+  // reserved before one starts).
+  hipError_t reserve(size_t n, bool zero = false) {
     if (n <= bytes) return hipSuccess;
     if (ptr) {
       hipError_t e = hipDeviceSynchronize();
@@ -50,7 +53,7 @@ struct DevBuf {
       return e;
     }
     bytes = want;
-    return hipSuccess;
+    return zero ? hipMemset(ptr, 0, want) : hipSuccess;
   }
   template <typename T>
   T* as() const {
@@ -355,7 +358,8 @@ ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
                          16};
   for (int b = 0; b < 9; ++b) {
     void* before = bufs[b]->ptr;
-    HIP_TRY(ctx, bufs[b]->reserve(want[b]), "allocate workspace");
+    // the status flag is read before anything has written it
+    HIP_TRY(ctx, bufs[b]->reserve(want[b], bufs[b] == &ctx->flag), "allocate workspace");
     if (before && bufs[b]->ptr != before) ctx->graphs.clear();
   }
   return FFA_OK;
@@ -758,7 +762,7 @@ ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int
   const int32_t bps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2048, nsamp / 4096));
   HIP_TRY(ctx, ctx->partials.reserve((size_t)bps * 2 * sizeof(double)), "allocate");
   HIP_TRY(ctx, ctx->norm.reserve(2 * sizeof(float)), "allocate");
-  HIP_TRY(ctx, ctx->flag.reserve(16), "allocate");
+  HIP_TRY(ctx, ctx->flag.reserve(16, true), "allocate");
   HIP_TRY(ctx, launch_stats(tmp.as<SeriesDev>(), 1, dtype, bps, ctx->partials.as<double>(),
                             stats_dev, ctx->norm.as<float>(), ctx->flag.as<int32_t>(), st),
           "stats kernels");

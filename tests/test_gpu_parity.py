@@ -188,6 +188,21 @@ def test_degenerate_series_sets_status(ctx):
     assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
 
 
+def test_fresh_context_reports_ok_status():
+    # the status word of a new context starts cleared (its memory may hold
+    # anything before the first search writes it)
+    junk = torch.full((1 << 20,), -1, dtype=torch.int32, device="cuda")
+    del junk
+    c = ffa.ffa_create(0)
+    try:
+        x = np.random.default_rng(12).standard_normal(20_000).astype(np.float32)
+        prm = ffa.make_params(1.0, 40.0, 400.0, 40, 47, (1, 2))
+        ffa.ffa_search(c, dev(x), prm)
+        assert ffa.ffa_sync_status(c) == ffa.FFA_OK
+    finally:
+        ffa.ffa_destroy(c)
+
+
 def test_invalid_arguments_do_no_device_work(ctx):
     x = dev(np.zeros(1000, np.float32))
     prm = ffa.make_params(1.0, 40.0, 400.0, 40, 47, (1, 2))
