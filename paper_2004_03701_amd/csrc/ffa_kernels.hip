@@ -3,8 +3,10 @@
 //   k_stats_*      FP64 mean / population std of each series (Sec. 5.2)
 //   k_downsample   every pseudo-octave of a series in one read of it
 //                  (Sec. 5.3, App. A.4)
-//   k_ffa_pass     folding-transform tiles in LDS (Sec. 2.2) and, for the
-//                  rows of the full transform, the boxcar S/N (Sec. 5.4)
+//   k_ffa_pass     folding-transform tiles (Sec. 2.2): the bottom merge
+//                  levels in registers, the upper ones as paired merges in
+//                  LDS, and for the rows of the full transform the boxcar
+//                  S/N (Sec. 5.4)
 //
 // None of the paths is a dense contraction, so nothing here uses MFMA: the
 // limits are HBM bandwidth (stats, downsampling) and LDS / VALU throughput
@@ -556,8 +558,9 @@ __device__ __forceinline__ int ceil_log2(int n) {
 }
 
 // Slot <-> (row of the wave, column iteration) mapping shared by the load,
-// merge and store phases: slot = r * J + j, row q = wave + 16 r, column
-// group lane + 64 j. JS = 1 fixes J = 1 at compile time (p <= 320).
+// merge and store phases: slot = r * J + j, row q = wave + WV r, column
+// group lane + 64 j. JS = 1 fixes J = 1 at compile time (one column group
+// per lane).
 template <int JS>
 struct Slots {
   int J;
@@ -572,8 +575,10 @@ struct LaneOp {
   int h, t, rot;
 };
 
-// One merge level, in place, for waves whose rows fit in NS slots: a wave
-// takes output rows wave, wave + 16, ...; lane l owns the column groups
+// One merge level of single rows, in place (the all-LDS form, for rows too
+// wide for the register levels and the pair merges), for waves whose rows
+// fit in NS slots: a wave takes output rows wave, wave + WV, ...; lane l
+// owns the column groups
 // l, l + 64, ... of kChunk columns. All reads of a lane are issued first, the
 // workgroup synchronises, then the outputs are written back. Groups that
 // start past p compute the row's wrapped copy; lanes and slots with nothing
@@ -1425,12 +1430,12 @@ __device__ __forceinline__ void snr_grid(const float* rows, int stride, int p, i
 constexpr int kSnrSeg = 32;
 
 // The register-window form needs the window of a segment that starts below p
-// to end, after one wrap, within the row's copied bins (below p + kChunk - 1),
-// and the row area to hold the partial maxima of one segment per wave.
+// to end, after one wrap, within the row's kHalo copied bins, and the row
+// area to hold the partial maxima of one segment per wave.
 template <class G>
 __device__ __forceinline__ bool snr_seg_fits(int p, int nvalid, int region_floats) {
   constexpr int NV = kSnrSeg + G::kMax - 1;
-  return p >= NV - kChunk && region_floats >= G::kN * 64 * ((nvalid + 63) >> 6);
+  return p >= NV - kHalo && region_floats >= G::kN * 64 * ((nvalid + 63) >> 6);
 }
 
 template <class G, bool kWrap>
