@@ -31,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue of the chip without packed FP32 (the kernels are built
+# with packed FP32 disabled): 256 CUs x 64 lanes x 2.4 GHz, one op per lane
+# and cycle, in 10^12 op/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def parse():
@@ -106,6 +110,47 @@ def committed_traffic(workload, storage):
     if rec.get("kernel_src_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_step", {}).get(f"{workload}:{storage}")
+
+
+def merge_rows(n, memo={}):
+    """Rows produced by the merges of an n-row FFA tree (head floor(n/2),
+    tail the rest, Sec. 2.2); each produced row costs p additions."""
+    if n <= 1:
+        return 0
+    if n not in memo:
+        memo[n] = n + merge_rows(n // 2) + merge_rows(n - n // 2)
+    return memo[n]
+
+
+def alg_ops_per_series(plan, num_widths):
+    """Algorithmic FP32 operations of the fold kernel for one series: the
+    merge additions of every transform plus, per kept profile, the prefix
+    (p additions) and per width one subtraction and one maximum per phase."""
+    xf = {}
+    for k, p, m in zip(plan["octave"], plan["bins"], plan["m"]):
+        xf[(int(k), int(p))] = int(m)
+    merges = sum(p * merge_rows(m) for (_, p), m in xf.items())
+    snr = int(plan["bins"].astype(np.int64).sum()) * (1 + 2 * num_widths)
+    return merges + snr
+
+
+def copy_ceiling(torch, mib=1024, reps=10):
+    """GB/s of a plain device-to-device copy (read + write bytes), the
+    practical ceiling of an HBM-bound kernel."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def cpu_baseline(seconds, nsamp):
@@ -201,6 +246,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {a.calib_copy_mib} MiB done")
         del src, dst
+    copy_gbs = copy_ceiling(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     nsamp = 1 << a.log2n
     cfg = synth.workload3_config()
     x32 = make_inputs(torch, a.series, nsamp)
@@ -218,7 +265,9 @@ def main():
                                cfg.bins_max, cfg.widths, normalise=True, dtype=dt_code)
                for _ in range(a.series)]
         rows1 = ffa.ffa_plan_rows(prm[0], nsamp)
-        bins = ffa.ffa_plan_export(prm[0], nsamp)["bins"].astype(np.int64)
+        plan = ffa.ffa_plan_export(prm[0], nsamp)
+        bins = plan["bins"].astype(np.int64)
+        alg_ops = a.series * alg_ops_per_series(plan, len(cfg.widths))
         snr = torch.empty((rows1 * a.series, len(cfg.widths)), dtype=torch.float32,
                           device="cuda")
         tiling = None
@@ -265,13 +314,15 @@ def main():
         alg_bytes = a.series * (int(bins.sum()) * esize + rows1 * len(cfg.widths) * 4)
         fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
         res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),
-               "profiles": profiles, "alg_bytes_fold": alg_bytes, "timing": tm,
+               "profiles": profiles, "alg_bytes_fold": alg_bytes, "alg_ops_fold": alg_ops,
+               "timing": tm,
                "tiling": tiling, "eager_ms_per_step": 1e3 * wall_eager / a.steps,
                "graph_ms_per_step": graph_ms}
         if fold_ms:
             res["fold_ms_per_step"] = fold_ms
             res["fold_launches_per_step"] = tm["fold_launches"] / a.steps
             res["fold_alg_GBps"] = alg_bytes / (fold_ms * 1e-3) / 1e9
+            res["fold_alg_Tops"] = alg_ops / (fold_ms * 1e-3) / 1e12
             res["stats_ms_per_step"] = tm["stats_ms"] / a.steps
             res["downsample_ms_per_step"] = tm["downsample_ms"] / a.steps
         results[v] = res
@@ -304,7 +355,11 @@ def main():
                            "frac": ach / HBM_PEAK_GBS,
                            "traffic": (tb / (r["fold_ms_per_step"] * 1e-3) / 1e9) if tb else None,
                            "kernel": "k_ffa_pass (all fold launches of a step)",
-                           "fold_ms_per_step": r["fold_ms_per_step"]}
+                           "fold_ms_per_step": r["fold_ms_per_step"],
+                           "copy_GBps": copy_gbs, "frac_of_copy": ach / copy_gbs,
+                           "alu": {"achieved": r["fold_alg_Tops"], "peak": VALU_PEAK_TOPS,
+                                   "unit": "Top/s",
+                                   "frac": r["fold_alg_Tops"] / VALU_PEAK_TOPS}}
     out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "timing"}
                        for k, v in results.items()}
     if "f32" in results and head != "f32":
