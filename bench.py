@@ -49,6 +49,9 @@ def parse():
                     help="1: after the per-kernel timed steps, time the same steps again as "
                          "hipGraph replays (the headline value); 0: eager launches only")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--peaks", type=int, default=1,
+                    help="1: also time peak detection (Sec. 5.5) on the headline variant's "
+                         "periodograms, reported apart from the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="batch", choices=["batch", "uneven"])
     ap.add_argument("--autotune", type=int, default=0,
@@ -151,6 +154,37 @@ def copy_ceiling(torch, mib=1024, reps=10):
     del src, dst
     torch.cuda.empty_cache()
     return gbs
+
+
+def bench_peaks(ffa, ctx, snr, prm, nsamp, rows1, a):
+    """Peak detection of every series' periodogram, timed per kernel with HIP
+    events (three launches per call) and by wall clock (the call includes its
+    host work and the copy of the peaks to the host)."""
+    import torch
+    n = len(prm)
+    ro = [i * rows1 for i in range(n)]
+    ns = [nsamp] * n
+    pp = ffa.make_peak_params()
+    ffa.ffa_find_peaks_batch(ctx, snr, prm, ns, ro, pp, capacity=1 << 22)
+    torch.cuda.synchronize()
+    ffa.ffa_set_timing(ctx, True)
+    ffa.ffa_read_timing(ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        got, counts, _ = ffa.ffa_find_peaks_batch(ctx, snr, prm, ns, ro, pp, capacity=1 << 22)
+    wall = (time.perf_counter() - t0) / a.steps
+    tm = ffa.ffa_read_timing(ctx, reset=True)
+    ffa.ffa_set_timing(ctx, False)
+    kms = tm["peaks_ms"] / a.steps
+    # the S/N array is read twice (control points, then the scan); the
+    # frequency tables (16 B per row of the shared plan) once
+    alg = 2 * snr.shape[0] * snr.shape[1] * 4 + 16 * rows1
+    gbs = alg / (kms * 1e-3) / 1e9
+    return {"ms_per_call": 1e3 * wall, "kernel_ms": kms,
+            "launches_per_call": tm["peaks_launches"] / a.steps, "alg_bytes": alg,
+            "alg_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS, "peaks_found": int(counts.sum()),
+            "params": {"dz_seg": pp.dz_seg, "k_sigma": pp.k_sigma, "degree": pp.degree,
+                       "min_points": pp.min_points, "cluster_gap": pp.cluster_gap}}
 
 
 def cpu_baseline(seconds, nsamp):
@@ -325,6 +359,8 @@ def main():
             res["fold_alg_Tops"] = alg_ops / (fold_ms * 1e-3) / 1e12
             res["stats_ms_per_step"] = tm["stats_ms"] / a.steps
             res["downsample_ms_per_step"] = tm["downsample_ms"] / a.steps
+        if a.peaks and v == variants[0]:
+            res["peaks"] = bench_peaks(ffa, ctx, snr, prm, nsamp, rows1, a)
         results[v] = res
         del series, xs, snr
         torch.cuda.empty_cache()
@@ -360,7 +396,9 @@ def main():
                            "alu": {"achieved": r["fold_alg_Tops"], "peak": VALU_PEAK_TOPS,
                                    "unit": "Top/s",
                                    "frac": r["fold_alg_Tops"] / VALU_PEAK_TOPS}}
-    out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk != "timing"}
+    if "peaks" in r:
+        out["peaks"] = r["peaks"]
+    out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk not in ("timing", "peaks")}
                        for k, v in results.items()}
     if "f32" in results and head != "f32":
         out["speedup_vs_f32"] = results[head]["profiles_per_s"] / results["f32"]["profiles_per_s"]

@@ -193,6 +193,59 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
                         const int64_t* nsamp, const ffa_search_params* params,
                         const char* cache_path, ffa_tiling* best, void* stream);
 
+/* Periodogram peak detection (Sec. 5.5 and its peak-detection figure).
+ * Each width trial is searched on its own. Its S/N against trial frequency
+ * nu = 1 / P is cut into segments of width dz_seg / T (T = nsamp * tsamp,
+ * the length of the series; segment i covers [nu_lo + i dnu, nu_lo +
+ * (i + 1) dnu), nu_lo the lowest trial frequency). A segment of at least
+ * min_points rows, all finite, gives a control point at its centre
+ * frequency: median + k_sigma * IQR / 1.349, the quartiles taken by linear
+ * interpolation between order statistics. A polynomial of the given degree
+ * in log(nu), fitted to the control points by unweighted least squares, is
+ * the threshold (none with fewer than degree + 1 control points). The rows
+ * whose S/N exceeds it form clusters, in frequency order, while consecutive
+ * members are at most cluster_gap / T apart; a peak is the brightest member
+ * of a cluster (the first in row order on equal S/N). */
+typedef struct {
+  double dz_seg;       /* segment width in units of 1 / T, > 0 (the paper: a few) */
+  double k_sigma;      /* threshold height in robust sigmas (the paper's default: 6) */
+  int32_t degree;      /* polynomial degree, 0..4 (the paper's default: 2) */
+  int32_t min_points;  /* fewest rows of a segment with a control point, >= 1 */
+  double cluster_gap;  /* largest frequency step inside a cluster, units of 1 / T, >= 0 */
+} ffa_peak_params;
+
+typedef struct {
+  int64_t row;         /* row of the peak's brightest member in its series' periodogram */
+  double period;       /* trial period of that row, seconds */
+  double threshold;    /* threshold at that row */
+  float snr;           /* S/N of that row and width */
+  int32_t series;      /* index of the series in the call */
+  int32_t width_index; /* index of the boxcar width */
+  int32_t members;     /* rows above the threshold in the cluster */
+} ffa_peak;
+
+/* Peaks of the periodograms of nseries series, as written by
+ * ffa_search_batch with the same nsamp, params and row_offset (HOST arrays of
+ * nseries; num_widths equal across series). snr_dev (DEVICE, capacity_rows x
+ * num_widths FP32) is read only. Every segment may hold at most 8192 rows
+ * (FFA_ERR_INVALID_ARG otherwise; lower dz_seg).
+ *   peaks_host   HOST, capacity_peaks records: the peaks ordered by series,
+ *                width and row. Not written when there are more peaks than
+ *                capacity_peaks; the call then returns FFA_ERR_BUFFER_TOO_SMALL.
+ *   npeaks_host  HOST, nseries counts of peaks per series (always written on
+ *                success and on FFA_ERR_BUFFER_TOO_SMALL).
+ *   poly_host    HOST, nseries x num_widths x (degree + 1) doubles, or NULL:
+ *                the threshold's coefficients c_0 .. c_degree in powers of
+ *                log(nu); NaN for a width without a threshold.
+ * The call waits for `stream`. A periodogram with non-finite S/N (a
+ * degenerate series) gives no control point in the segments it touches. */
+ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* nsamp,
+                                const ffa_search_params* params, const int64_t* row_offset,
+                                const float* snr_dev, int64_t capacity_rows,
+                                const ffa_peak_params* peak_params, ffa_peak* peaks_host,
+                                int64_t capacity_peaks, int64_t* npeaks_host, double* poly_host,
+                                void* stream);
+
 /* Per-kernel device time of the calls made while timing is on. Each launch
  * is bracketed by HIP events on the stream it runs on (not inside captured
  * graphs). */
@@ -207,6 +260,8 @@ typedef struct {
   int64_t folded_cells;        /* sum of m * p over the transforms folded */
   int64_t input_samples;       /* raw samples read */
   int64_t downsampled_samples; /* samples written by the downsampler */
+  double peaks_ms;             /* peak-detection kernels (Sec. 5.5) */
+  int64_t peaks_launches;
 } ffa_kernel_times;
 
 /* Turns per-kernel timing on (1) or off (0) for the calls that follow. */

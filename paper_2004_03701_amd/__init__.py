@@ -35,7 +35,7 @@ EXPORTED = (
     "ffa_create", "ffa_destroy", "ffa_status_string", "ffa_last_error", "ffa_plan_rows",
     "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
     "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
-    "ffa_set_timing", "ffa_read_timing",
+    "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch",
 )
 
 
@@ -70,10 +70,31 @@ class ffa_kernel_times(ctypes.Structure):
         ("folded_cells", ctypes.c_int64),
         ("input_samples", ctypes.c_int64),
         ("downsampled_samples", ctypes.c_int64),
+        ("peaks_ms", ctypes.c_double),
+        ("peaks_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ffa_peak_params(ctypes.Structure):
+    _fields_ = [("dz_seg", ctypes.c_double), ("k_sigma", ctypes.c_double),
+                ("degree", ctypes.c_int32), ("min_points", ctypes.c_int32),
+                ("cluster_gap", ctypes.c_double)]
+
+
+class ffa_peak(ctypes.Structure):
+    _fields_ = [("row", ctypes.c_int64), ("period", ctypes.c_double),
+                ("threshold", ctypes.c_double), ("snr", ctypes.c_float),
+                ("series", ctypes.c_int32), ("width_index", ctypes.c_int32),
+                ("members", ctypes.c_int32)]
+
+
+PEAK_DTYPE = np.dtype([("row", np.int64), ("period", np.float64), ("threshold", np.float64),
+                       ("snr", np.float32), ("series", np.int32), ("width_index", np.int32),
+                       ("members", np.int32)], align=True)
+assert PEAK_DTYPE.itemsize == ctypes.sizeof(ffa_peak)
 
 
 class FFAError(RuntimeError):
@@ -115,6 +136,8 @@ def lib() -> ctypes.CDLL:
         "ffa_autotune": ([vp, i32, P(vp), P(i64), pp, ctypes.c_char_p, P(ffa_tiling), vp], i32),
         "ffa_set_timing": ([vp, i32], i32),
         "ffa_read_timing": ([vp, P(ffa_kernel_times), i32], i32),
+        "ffa_find_peaks_batch": ([vp, i32, P(i64), pp, P(i64), vp, i64, P(ffa_peak_params), vp,
+                                  i64, P(i64), vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -308,3 +331,37 @@ def ffa_read_timing(ctx, reset: bool = True) -> dict:
     t = ffa_kernel_times()
     _check(lib().ffa_read_timing(ctx, ctypes.byref(t), 1 if reset else 0), ctx)
     return t.as_dict()
+
+
+def make_peak_params(dz_seg: float = 4.0, k_sigma: float = 6.0, degree: int = 2,
+                     min_points: int = 16, cluster_gap: float = 1.0) -> ffa_peak_params:
+    return ffa_peak_params(float(dz_seg), float(k_sigma), int(degree), int(min_points),
+                           float(cluster_gap))
+
+
+def ffa_find_peaks_batch(ctx, snr, params: Sequence[ffa_search_params], nsamp: Sequence[int],
+                         row_offset: Sequence[int], peak_params: Optional[ffa_peak_params] = None,
+                         capacity: int = 1 << 16, stream=None):
+    """Peaks of the periodograms in `snr` (a device tensor written by
+    ffa_search_batch). Returns (peaks: structured array of PEAK_DTYPE ordered
+    by series, width and row; counts per series; threshold coefficients,
+    series x widths x (degree + 1)). Raises FFAError with status
+    FFA_ERR_BUFFER_TOO_SMALL when more than `capacity` peaks are found."""
+    if peak_params is None:
+        peak_params = make_peak_params()
+    n = len(params)
+    ns = (ctypes.c_int64 * n)(*[int(v) for v in nsamp])
+    prm = (ffa_search_params * n)(*params)
+    ro = (ctypes.c_int64 * n)(*[int(v) for v in row_offset])
+    out = np.zeros(max(int(capacity), 1), dtype=PEAK_DTYPE)
+    counts = np.zeros(n, dtype=np.int64)
+    nw = params[0].num_widths
+    poly = np.zeros((n, nw, peak_params.degree + 1), dtype=np.float64)
+    st = lib().ffa_find_peaks_batch(
+        ctx, n, ns, prm, ro, snr.data_ptr(), snr.shape[0], ctypes.byref(peak_params),
+        out.ctypes.data, int(capacity), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        poly.ctypes.data, _stream(stream))
+    if st == FFA_ERR_BUFFER_TOO_SMALL:
+        raise FFAError(st, f"{int(counts.sum())} peaks found, capacity {capacity}")
+    _check(st, ctx)
+    return out[:int(counts.sum())].copy(), counts, poly

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <map>
 #include <memory>
@@ -17,6 +18,7 @@
 #include "../../include/ffa.h"
 #include "ffa_internal.hpp"
 #include "ffa_kernels.hpp"
+#include "ffa_peaks.hpp"
 #include "ffa_plan.hpp"
 
 namespace ffa {
@@ -117,8 +119,18 @@ struct GraphEntry {
 }  // namespace
 
 // Event pairs bracketing timed launches.
+// Frequency tables of one plan for peak detection (Sec. 5.5): every row's
+// trial frequency and its log, and the rows of every frequency segment in
+// row order (rows ascend in period, so a segment is a run of rows).
+struct PeakPlan {
+  std::vector<double> nu, lognu;
+  std::vector<int32_t> seg_begin, seg_end;
+  std::vector<double> seg_x;  // log of the segment's centre frequency
+  int32_t max_seg = 0;        // rows of the largest segment
+};
+
 struct TimedLaunch {
-  int kind;  // 0 stats, 1 downsample, 2 fold
+  int kind;  // 0 stats, 1 downsample, 2 fold, 3 peak detection
   hipEvent_t start, stop;
 };
 
@@ -137,6 +149,11 @@ struct ffa_ctx {
   DevBuf full_ht, full_rot, full_off;  // merge schedules of full subtrees
   DevBuf full_pops, full_pops_off;      // their pair schedules
   DevBuf counters, ticket;              // persistent scheduler state
+  std::map<std::string, std::shared_ptr<PeakPlan>> peak_plans;
+  DevBuf pk_series, pk_nu, pk_lognu, pk_segb, pk_sege, pk_segx;  // peak-detection tables
+  DevBuf pk_ctrl, pk_fits, pk_peaks, pk_count;                    // and workspace
+  std::string pk_key;    // batch the peak-detection tables were uploaded for
+  int32_t pk_max_nseg = 0, pk_max_seg = 0;
   int num_cus = 256;
   size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
 };
@@ -560,6 +577,56 @@ ffa_status run_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   return FFA_OK;
 }
 
+// Frequency segments of a plan's rows (Sec. 5.5): nu = 1 / P, segment
+// floor((nu - nu_lo) / dnu) with dnu = dz_seg / T, all in FP64.
+ffa_status build_peak_plan(ffa_ctx* ctx, const SeriesPlan& plan, double T, double dz_seg,
+                           PeakPlan* out) {
+  const int64_t R = plan.rows;
+  if (R >= (int64_t(1) << 31)) return fail(ctx, FFA_ERR_INVALID_ARG, "too many periodogram rows");
+  out->nu.resize(R);
+  out->lognu.resize(R);
+  for (const Transform& t : plan.tr) {
+    const Octave& o = plan.oct[t.octave];
+    for (int32_t r = 0; r < t.keep; ++r) {
+      const double nu = 1.0 / trial_period(r, t.m, t.p, o.tau);
+      out->nu[t.row0 + r] = nu;
+      out->lognu[t.row0 + r] = std::log(nu);
+    }
+  }
+  if (R == 0) return FFA_OK;
+  const double nu_lo = *std::min_element(out->nu.begin(), out->nu.end());
+  const double dnu = dz_seg / T;
+  int64_t cur = -1;
+  for (int64_t r = 0; r < R; ++r) {
+    const int64_t id = (int64_t)std::floor((out->nu[r] - nu_lo) / dnu);
+    if (r > 0 && id > cur)
+      return fail(ctx, FFA_ERR_DEVICE, "trial frequencies are not descending along the rows");
+    if (r == 0 || id != cur) {
+      if (r > 0) out->seg_end.push_back((int32_t)r);
+      out->seg_begin.push_back((int32_t)r);
+      out->seg_x.push_back(std::log(nu_lo + ((double)id + 0.5) * dnu));
+      cur = id;
+    }
+  }
+  out->seg_end.push_back((int32_t)R);
+  for (size_t i = 0; i < out->seg_begin.size(); ++i)
+    out->max_seg = std::max(out->max_seg, out->seg_end[i] - out->seg_begin[i]);
+  return FFA_OK;
+}
+
+// Power-basis coefficients in x of sum_j c_j ((x - xbar) s)^j.
+void expand_poly(const PeakFitDev& f, int degree, double* out) {
+  for (int j = 0; j <= degree; ++j) out[j] = 0.0;
+  // binomial expansion of (s x - s xbar)^j
+  for (int j = 0; j <= degree; ++j) {
+    double binom = 1.0;  // C(j, l)
+    for (int l = 0; l <= j; ++l) {
+      out[l] += f.c[j] * binom * std::pow(f.inv_scale, j) * std::pow(-f.xbar, j - l);
+      binom = binom * (j - l) / (l + 1);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -860,9 +927,12 @@ ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset) {
     } else if (t.kind == 1) {
       ctx->times.downsample_ms += ms;
       ctx->times.downsample_launches += 1;
-    } else {
+    } else if (t.kind == 2) {
       ctx->times.fold_ms += ms;
       ctx->times.fold_launches += 1;
+    } else {
+      ctx->times.peaks_ms += ms;
+      ctx->times.peaks_launches += 1;
     }
     ctx->event_pool.push_back(t.start);
     ctx->event_pool.push_back(t.stop);
@@ -990,6 +1060,193 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
               winner.persistent, winner.waves);
       fclose(f);
     }
+  }
+  return FFA_OK;
+}
+
+ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* nsamp,
+                                const ffa_search_params* params, const int64_t* row_offset,
+                                const float* snr_dev, int64_t capacity_rows,
+                                const ffa_peak_params* pp, ffa_peak* peaks_host,
+                                int64_t capacity_peaks, int64_t* npeaks_host, double* poly_host,
+                                void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (nseries < 1 || !nsamp || !params || !row_offset || !snr_dev || !pp || !npeaks_host ||
+      capacity_peaks < 0 || (capacity_peaks > 0 && !peaks_host) || capacity_rows < 0)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "null argument, nseries < 1 or negative capacity");
+  if (!(pp->dz_seg > 0.0) || !std::isfinite(pp->dz_seg) || !std::isfinite(pp->k_sigma) ||
+      pp->degree < 0 || pp->degree > kPeakMaxDegree || pp->min_points < 1 ||
+      !(pp->cluster_gap >= 0.0) || !std::isfinite(pp->cluster_gap))
+    return fail(ctx, FFA_ERR_INVALID_ARG,
+                "peak parameters: dz_seg > 0, finite k_sigma, degree 0..4, min_points >= 1, "
+                "finite cluster_gap >= 0");
+  const int32_t nw = params[0].num_widths;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "set device");
+  // plans and their frequency tables; the device tables (one copy per
+  // distinct plan, and the series table) are uploaded again only when the
+  // batch differs from the previous call's
+  std::vector<std::shared_ptr<SeriesPlan>> plans(nseries);
+  std::vector<std::shared_ptr<PeakPlan>> pks(nseries);
+  std::vector<std::string> keys(nseries);
+  std::ostringstream call_key;
+  call_key.precision(17);
+  call_key << nseries << '|' << pp->cluster_gap << '|';
+  for (int32_t i = 0; i < nseries; ++i) {
+    if (params[i].num_widths != nw)
+      return fail(ctx, FFA_ERR_INVALID_ARG, "all series need the same number of widths");
+    ffa_status rs = get_plan(ctx, params[i], nsamp[i], &plans[i]);
+    if (rs != FFA_OK) return rs;
+    const SeriesPlan& plan = *plans[i];
+    if (row_offset[i] < 0 || row_offset[i] + plan.rows > capacity_rows)
+      return fail(ctx, FFA_ERR_INVALID_ARG, "series rows past capacity_rows");
+    std::ostringstream key;
+    key.precision(17);
+    key << plan_key(params[i], nsamp[i]) << '|' << pp->dz_seg;
+    keys[i] = key.str();
+    auto it = ctx->peak_plans.find(keys[i]);
+    if (it != ctx->peak_plans.end()) {
+      pks[i] = it->second;
+    } else {
+      pks[i] = std::make_shared<PeakPlan>();
+      ffa_status bs = build_peak_plan(ctx, plan, (double)nsamp[i] * params[i].tsamp,
+                                      pp->dz_seg, pks[i].get());
+      if (bs != FFA_OK) return bs;
+      ctx->peak_plans[keys[i]] = pks[i];
+    }
+    call_key << keys[i] << '@' << row_offset[i] << ';';
+  }
+  if (call_key.str() != ctx->pk_key) {
+    ctx->pk_key.clear();
+    std::vector<PeakSeriesDev> sdev(nseries);
+    std::vector<double> nu, lognu, segx;
+    std::vector<int32_t> segb, sege;
+    std::map<std::string, std::pair<int64_t, int32_t>> placed;  // key -> (freq0, seg0)
+    int32_t max_nseg = 0, max_seg = 0;
+    for (int32_t i = 0; i < nseries; ++i) {
+      const PeakPlan& pk = *pks[i];
+      auto pl = placed.find(keys[i]);
+      if (pl == placed.end()) {
+        pl = placed.emplace(keys[i], std::make_pair((int64_t)nu.size(), (int32_t)segb.size())).first;
+        nu.insert(nu.end(), pk.nu.begin(), pk.nu.end());
+        lognu.insert(lognu.end(), pk.lognu.begin(), pk.lognu.end());
+        segb.insert(segb.end(), pk.seg_begin.begin(), pk.seg_begin.end());
+        sege.insert(sege.end(), pk.seg_end.begin(), pk.seg_end.end());
+        segx.insert(segx.end(), pk.seg_x.begin(), pk.seg_x.end());
+      }
+      PeakSeriesDev& d = sdev[i];
+      d.snr_row0 = row_offset[i];
+      d.rows = plans[i]->rows;
+      d.freq0 = pl->second.first;
+      d.seg0 = pl->second.second;
+      d.nseg = (int32_t)pk.seg_begin.size();
+      d.gap = pp->cluster_gap / ((double)nsamp[i] * params[i].tsamp);
+      max_nseg = std::max(max_nseg, d.nseg);
+      max_seg = std::max(max_seg, pk.max_seg);
+    }
+    if (max_seg > kPeakSegMax)
+      return fail(ctx, FFA_ERR_INVALID_ARG,
+                  "a frequency segment holds more than 8192 rows: lower dz_seg");
+    HIP_TRY(ctx, upload(ctx->pk_series, sdev), "upload peak series table");
+    HIP_TRY(ctx, upload(ctx->pk_nu, nu), "upload frequencies");
+    HIP_TRY(ctx, upload(ctx->pk_lognu, lognu), "upload log frequencies");
+    HIP_TRY(ctx, upload(ctx->pk_segb, segb), "upload segments");
+    HIP_TRY(ctx, upload(ctx->pk_sege, sege), "upload segments");
+    HIP_TRY(ctx, upload(ctx->pk_segx, segx), "upload segment centres");
+    ctx->pk_key = call_key.str();
+    ctx->pk_max_nseg = max_nseg;
+    ctx->pk_max_seg = max_seg;
+  }
+  const int32_t max_nseg = ctx->pk_max_nseg;
+  const size_t nfit = (size_t)nseries * nw;
+  HIP_TRY(ctx, ctx->pk_ctrl.reserve(std::max<size_t>(nfit * std::max(max_nseg, 1) * 8, 16)),
+          "peak control points");
+  HIP_TRY(ctx, ctx->pk_fits.reserve(nfit * sizeof(PeakFitDev)), "peak fits");
+  HIP_TRY(ctx, ctx->pk_peaks.reserve(std::max<int64_t>(capacity_peaks, 1) * sizeof(PeakDev)),
+          "peak records");
+  HIP_TRY(ctx, ctx->pk_count.reserve((size_t)(nseries + 1) * 4), "peak counters");
+  HIP_TRY(ctx, hipMemsetAsync(ctx->pk_count.ptr, 0, (size_t)(nseries + 1) * 4, st),
+          "clear peak counters");
+  PeakArgs a{};
+  a.series = ctx->pk_series.as<PeakSeriesDev>();
+  a.nseries = nseries;
+  a.num_widths = nw;
+  a.max_nseg = max_nseg;
+  a.degree = pp->degree;
+  a.min_points = pp->min_points;
+  a.k_sigma = pp->k_sigma;
+  a.snr = snr_dev;
+  a.nu = ctx->pk_nu.as<double>();
+  a.lognu = ctx->pk_lognu.as<double>();
+  a.seg_begin = ctx->pk_segb.as<int32_t>();
+  a.seg_end = ctx->pk_sege.as<int32_t>();
+  a.seg_x = ctx->pk_segx.as<double>();
+  a.ctrl = ctx->pk_ctrl.as<double>();
+  a.fits = ctx->pk_fits.as<PeakFitDev>();
+  a.peaks = ctx->pk_peaks.as<PeakDev>();
+  a.capacity = capacity_peaks;
+  a.count = ctx->pk_count.as<int32_t>();
+  {
+    TimedScope ts(ctx, 3, st, ctx->timing);
+    HIP_TRY(ctx, launch_peak_ctrl(a, ctx->pk_max_seg, st), "peak control-point kernels");
+  }
+  {
+    TimedScope ts(ctx, 3, st, ctx->timing);
+    HIP_TRY(ctx, launch_peak_fit(a, st), "peak fit kernel");
+  }
+  {
+    TimedScope ts(ctx, 3, st, ctx->timing);
+    HIP_TRY(ctx, launch_peak_scan(a, st), "peak scan kernel");
+  }
+  std::vector<int32_t> cnt(nseries + 1);
+  std::vector<PeakFitDev> fits(nfit);
+  HIP_TRY(ctx, hipMemcpyAsync(cnt.data(), ctx->pk_count.ptr, cnt.size() * 4, hipMemcpyDeviceToHost, st),
+          "read peak counters");
+  HIP_TRY(ctx, hipMemcpyAsync(fits.data(), ctx->pk_fits.ptr, nfit * sizeof(PeakFitDev),
+                              hipMemcpyDeviceToHost, st),
+          "read peak fits");
+  HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise peak detection");
+  for (int32_t i = 0; i < nseries; ++i) npeaks_host[i] = cnt[1 + i];
+  if (poly_host) {
+    const int nc = pp->degree + 1;
+    for (size_t q = 0; q < nfit; ++q) {
+      if (fits[q].ok)
+        expand_poly(fits[q], pp->degree, poly_host + q * nc);
+      else
+        for (int j = 0; j < nc; ++j) poly_host[q * nc + j] = NAN;
+    }
+  }
+  const int64_t total = cnt[0];
+  if (total > capacity_peaks)
+    return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "more peaks than capacity_peaks");
+  std::vector<PeakDev> pk(total);
+  if (total > 0) {
+    HIP_TRY(ctx, hipMemcpy(pk.data(), ctx->pk_peaks.ptr, total * sizeof(PeakDev), hipMemcpyDeviceToHost),
+            "read peaks");
+  }
+  std::sort(pk.begin(), pk.end(), [](const PeakDev& x, const PeakDev& y) {
+    if (x.series != y.series) return x.series < y.series;
+    if (x.width != y.width) return x.width < y.width;
+    return x.row < y.row;
+  });
+  for (int64_t q = 0; q < total; ++q) {
+    const PeakDev& d = pk[q];
+    const SeriesPlan& plan = *plans[d.series];
+    // period of the row from the plan (the same formula as ffa_plan_export)
+    double period = NAN;
+    for (const Transform& t : plan.tr)
+      if (d.row >= t.row0 && d.row < t.row0 + t.keep) {
+        period = trial_period(d.row - t.row0, t.m, t.p, plan.oct[t.octave].tau);
+        break;
+      }
+    ffa_peak& o = peaks_host[q];
+    o.row = d.row;
+    o.period = period;
+    o.threshold = d.threshold;
+    o.snr = d.snr;
+    o.series = d.series;
+    o.width_index = d.width;
+    o.members = d.members;
   }
   return FFA_OK;
 }
