@@ -150,10 +150,10 @@ struct ffa_ctx {
   DevBuf full_pops, full_pops_off;      // their pair schedules
   DevBuf counters, ticket;              // persistent scheduler state
   std::map<std::string, std::shared_ptr<PeakPlan>> peak_plans;
-  DevBuf pk_series, pk_nu, pk_lognu, pk_segb, pk_sege, pk_segx;  // peak-detection tables
+  DevBuf pk_series, pk_nu, pk_lognu, pk_segb, pk_sege, pk_segx, pk_mid, pk_big;  // peak-detection tables
   DevBuf pk_ctrl, pk_fits, pk_peaks, pk_count;                    // and workspace
   std::string pk_key;    // batch the peak-detection tables were uploaded for
-  int32_t pk_max_nseg = 0, pk_max_seg = 0;
+  int32_t pk_max_nseg = 0, pk_max_seg = 0, pk_nmid = 0, pk_nbig = 0;
   int num_cus = 256;
   size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
 };
@@ -1120,7 +1120,7 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
     ctx->pk_key.clear();
     std::vector<PeakSeriesDev> sdev(nseries);
     std::vector<double> nu, lognu, segx;
-    std::vector<int32_t> segb, sege;
+    std::vector<int32_t> segb, sege, mid, big;
     std::map<std::string, std::pair<int64_t, int32_t>> placed;  // key -> (freq0, seg0)
     int32_t max_nseg = 0, max_seg = 0;
     for (int32_t i = 0; i < nseries; ++i) {
@@ -1143,6 +1143,14 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
       d.gap = pp->cluster_gap / ((double)nsamp[i] * params[i].tsamp);
       max_nseg = std::max(max_nseg, d.nseg);
       max_seg = std::max(max_seg, pk.max_seg);
+      for (int32_t q = 0; q < d.nseg; ++q) {
+        const int32_t len = pk.seg_end[q] - pk.seg_begin[q];
+        if (len > kPeakWaveSortMax) {
+          std::vector<int32_t>& to = len > 2 * kPeakWaveSortMax ? big : mid;
+          to.push_back(i);
+          to.push_back(q);
+        }
+      }
     }
     if (max_seg > kPeakSegMax)
       return fail(ctx, FFA_ERR_INVALID_ARG,
@@ -1153,6 +1161,10 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
     HIP_TRY(ctx, upload(ctx->pk_segb, segb), "upload segments");
     HIP_TRY(ctx, upload(ctx->pk_sege, sege), "upload segments");
     HIP_TRY(ctx, upload(ctx->pk_segx, segx), "upload segment centres");
+    HIP_TRY(ctx, upload(ctx->pk_mid, mid), "upload large segments");
+    HIP_TRY(ctx, upload(ctx->pk_big, big), "upload large segments");
+    ctx->pk_nmid = (int32_t)(mid.size() / 2);
+    ctx->pk_nbig = (int32_t)(big.size() / 2);
     ctx->pk_key = call_key.str();
     ctx->pk_max_nseg = max_nseg;
     ctx->pk_max_seg = max_seg;
@@ -1181,6 +1193,10 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
   a.seg_begin = ctx->pk_segb.as<int32_t>();
   a.seg_end = ctx->pk_sege.as<int32_t>();
   a.seg_x = ctx->pk_segx.as<double>();
+  a.mid = ctx->pk_mid.as<int32_t>();
+  a.big = ctx->pk_big.as<int32_t>();
+  a.nmid = ctx->pk_nmid;
+  a.nbig = ctx->pk_nbig;
   a.ctrl = ctx->pk_ctrl.as<double>();
   a.fits = ctx->pk_fits.as<PeakFitDev>();
   a.peaks = ctx->pk_peaks.as<PeakDev>();
@@ -1188,7 +1204,7 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
   a.count = ctx->pk_count.as<int32_t>();
   {
     TimedScope ts(ctx, 3, st, ctx->timing);
-    HIP_TRY(ctx, launch_peak_ctrl(a, ctx->pk_max_seg, st), "peak control-point kernels");
+    HIP_TRY(ctx, launch_peak_ctrl(a, st), "peak control-point kernels");
   }
   {
     TimedScope ts(ctx, 3, st, ctx->timing);

@@ -6,12 +6,13 @@
 // selection threshold, and the points above it are clustered into peaks.
 //
 // Three steps:
-//   k_peak_ctrl_wave / k_peak_ctrl
+//   k_peak_ctrl_wave / k_peak_ctrl_pair / k_peak_ctrl
 //                the control points: one wave (segments of up to 1024 rows,
-//                sorted in registers) or one workgroup (larger segments,
-//                sorted in LDS) per (series, segment, width) sorts the
-//                segment's S/N values with a bitonic network and reads the
-//                quantiles from the order statistics;
+//                sorted in registers), two waves (up to 2048 rows, one stage
+//                through LDS) or one workgroup (larger segments, sorted in
+//                LDS) per (series, segment, width) sorts the segment's S/N
+//                values with a bitonic network and reads the quantiles from
+//                the order statistics;
 //   k_peak_fit   one wave per (series, width): power sums of the control
 //                points on a centred and scaled abscissa, reduced across the
 //                wave, and the normal equations solved in FP64;
@@ -60,7 +61,73 @@ __device__ __forceinline__ double quantile_sorted(const float* v, int n, double 
 // (exchanges inside a lane for partner distances below 16, across lanes with
 // shuffles above); padding with +inf keeps the network fixed. Element e of
 // the sorted order sits in register e % 16 of lane e / 16.
-constexpr int kWaveSortMax = 1024;
+constexpr int kWaveSortMax = kPeakWaveSortMax;
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
+}
+
+// The value of lane ^ D: quad permutations for D = 1, 2, row shifts for
+// 4, 8, a swizzle within 32 lanes for 16, a permute for 32.
+template <int D>
+__device__ __forceinline__ float from_lane_xor(float x, int lane) {
+  if constexpr (D == 1) return dpp_move<0xb1>(x);  // quad_perm [1, 0, 3, 2]
+  else if constexpr (D == 2) return dpp_move<0x4e>(x);  // quad_perm [2, 3, 0, 1]
+  else if constexpr (D == 4 || D == 8) {
+    // both moves run in every lane (a move reading a lane that a branch has
+    // switched off gets no data), then each lane keeps its partner's:
+    // row_shl:D reads lane + D, row_shr:D lane - D
+    const float above = dpp_move<0x100 + D>(x);
+    const float below = dpp_move<0x110 + D>(x);
+    return (lane & D) ? below : above;
+  }
+  else if constexpr (D == 16)
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x1f | (16 << 10)));
+  else return __shfl_xor(x, D, 64);
+}
+
+// One compare-exchange stage (block size K, partner distance J) of the
+// bitonic network over element e = e0 + 16 lane + r (e0: the first element
+// the wave holds).
+template <int K, int J>
+__device__ __forceinline__ void bitonic_stage(float (&v)[16], int lane, int e0) {
+  if constexpr (J < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r & J) continue;
+      const bool up = ((e0 + lane * 16 + r) & K) == 0;
+      const float x = v[r], y = v[r | J];
+      const bool sw = (x > y) == up;
+      v[r] = sw ? y : x;
+      v[r | J] = sw ? x : y;
+    }
+  } else {
+    constexpr int D = J >> 4;
+    const bool lower = (lane & D) == 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const bool up = ((e0 + lane * 16 + r) & K) == 0;
+      const float x = v[r], y = from_lane_xor<D>(x, lane);
+      v[r] = (lower == up) ? fminf(x, y) : fmaxf(x, y);
+    }
+  }
+}
+
+// Stages J, J / 2, ..., 1 of block size K.
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge(float (&v)[16], int lane, int e0) {
+  bitonic_stage<K, J>(v, lane, e0);
+  if constexpr (J > 1) bitonic_merge<K, J / 2>(v, lane, e0);
+}
+
+// Block sizes K, 2K, ..., kWaveSortMax: the wave's 1024 elements end sorted
+// ascending if bit 10 of e0 is clear, descending if set.
+template <int K>
+__device__ __forceinline__ void bitonic_sort(float (&v)[16], int lane, int e0) {
+  bitonic_merge<K, K / 2>(v, lane, e0);
+  if constexpr (K < kWaveSortMax) bitonic_sort<K * 2>(v, lane, e0);
+}
 
 __device__ __forceinline__ float pick16(const float (&v)[16], int r) {
   float x = v[0];
@@ -114,49 +181,78 @@ __global__ __launch_bounds__(64) void k_peak_ctrl_wave(PeakArgs a) {
     if (lane == 0) *out = NAN;
     return;
   }
-#pragma unroll
-  for (int k = 2; k <= kWaveSortMax; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j < 16) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (r & j) continue;
-          const int e = lane * 16 + r;
-          const bool up = (e & k) == 0;
-          const float x = v[r], y = v[r | j];
-          const bool sw = (x > y) == up;
-          v[r] = sw ? y : x;
-          v[r | j] = sw ? x : y;
-        }
-      } else {
-        const int d = j >> 4;
-        const bool lower = (lane & d) == 0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int e = lane * 16 + r;
-          const bool up = (e & k) == 0;
-          const float x = v[r], y = __shfl_xor(x, d, 64);
-          v[r] = (lower == up) ? fminf(x, y) : fmaxf(x, y);
-        }
-      }
-    }
-  }
+  bitonic_sort<2>(v, lane, 0);
   const double med = wave_quantile(v, n, 0.5);
   const double iqr = wave_quantile(v, n, 0.75) - wave_quantile(v, n, 0.25);
   if (lane == 0) *out = med + a.k_sigma * iqr / 1.349;
 }
 
-// Segments of kWaveSortMax + 1 .. kPeakSegMax rows: one workgroup sorts them
-// in LDS.
-__global__ __launch_bounds__(kPeakThreads) void k_peak_ctrl(PeakArgs a) {
-  __shared__ float v[kPeakSegMax];
-  const int s = blockIdx.x / a.max_nseg, i = blockIdx.x - s * a.max_nseg, w = blockIdx.y;
+// Segments of kWaveSortMax + 1 .. 2 kWaveSortMax rows (the a.nmid pairs of
+// a.mid): two waves of a workgroup hold 1024 elements each and sort them in
+// opposite directions, the one stage of partner distance 1024 exchanges
+// through LDS, and each wave finishes its half in registers.
+__global__ __launch_bounds__(128) void k_peak_ctrl_pair(PeakArgs a) {
+  __shared__ float xs[2 * kWaveSortMax];
+  const int s = a.mid[2 * blockIdx.x], i = a.mid[2 * blockIdx.x + 1], w = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const PeakSeriesDev sd = a.series[s];
-  if (i >= sd.nseg) return;
   double* out = a.ctrl + ((int64_t)s * a.num_widths + w) * a.max_nseg + i;
   const int rb = a.seg_begin[sd.seg0 + i], n = a.seg_end[sd.seg0 + i] - rb;
-  if (n <= kWaveSortMax) return;  // the register form takes it
+  if (n < a.min_points) {
+    if (threadIdx.x == 0) *out = NAN;
+    return;
+  }
+  const float* col = a.snr + (sd.snr_row0 + rb) * a.num_widths + w;
+  const int e0 = wave * kWaveSortMax;
+  float v[16];
+  int bad = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int e = e0 + r * 64 + lane;  // a multiset: any assignment will do
+    float x = INFINITY;
+    if (e < n) {
+      x = col[(int64_t)e * a.num_widths];
+      if (!isfinite(x)) {
+        bad = 1;
+        x = INFINITY;
+      }
+    }
+    v[r] = x;
+  }
+  if (__syncthreads_or(bad)) {
+    if (threadIdx.x == 0) *out = NAN;
+    return;
+  }
+  bitonic_sort<2>(v, lane, e0);  // wave 0 ascending, wave 1 descending
+  // stage K = 2048, J = 1024: wave 0 keeps the minima, wave 1 the maxima
+#pragma unroll
+  for (int r = 0; r < 16; ++r) xs[e0 + lane * 16 + r] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float y = xs[(e0 ^ kWaveSortMax) + lane * 16 + r];
+    v[r] = wave == 0 ? fminf(v[r], y) : fmaxf(v[r], y);
+  }
+  bitonic_merge<2 * kWaveSortMax, kWaveSortMax / 2>(v, lane, e0);
+  __syncthreads();  // every wave has read the exchange
+#pragma unroll
+  for (int r = 0; r < 16; ++r) xs[e0 + lane * 16 + r] = v[r];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double med = quantile_sorted(xs, n, 0.5);
+    const double iqr = quantile_sorted(xs, n, 0.75) - quantile_sorted(xs, n, 0.25);
+    *out = med + a.k_sigma * iqr / 1.349;
+  }
+}
+
+// Segments of 2 kWaveSortMax + 1 .. kPeakSegMax rows (the a.nbig pairs of
+// a.big): one workgroup sorts them in LDS.
+__global__ __launch_bounds__(kPeakThreads) void k_peak_ctrl(PeakArgs a) {
+  __shared__ float v[kPeakSegMax];
+  const int s = a.big[2 * blockIdx.x], i = a.big[2 * blockIdx.x + 1], w = blockIdx.y;
+  const PeakSeriesDev sd = a.series[s];
+  double* out = a.ctrl + ((int64_t)s * a.num_widths + w) * a.max_nseg + i;
+  const int rb = a.seg_begin[sd.seg0 + i], n = a.seg_end[sd.seg0 + i] - rb;
   if (n < a.min_points || n > kPeakSegMax) {
     if (threadIdx.x == 0) *out = NAN;
     return;
@@ -311,13 +407,21 @@ __device__ __forceinline__ void emit_peak(const PeakArgs& a, int s, int w, int64
 
 // Rows per thread and chunk of the scan: their loads are issued together.
 constexpr int kScanRows = 4;
+// Finished peaks a scan workgroup holds before writing them out together.
+constexpr int kPeakBuf = 128;
 
 __global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
   constexpr int kWaves = kPeakThreads / 64, kChunkRows = kScanRows * kPeakThreads;
-  __shared__ int64_t lrow[kChunkRows];
+  // rows above the threshold in the current chunk, in row order
+  __shared__ int32_t lrow[kChunkRows];
   __shared__ float lsnr[kChunkRows];
-  __shared__ double lthr[kChunkRows];
+  __shared__ double lthr[kChunkRows], lnu[kChunkRows];
   __shared__ int wcount[kScanRows][kWaves];
+  // finished peaks not yet written
+  __shared__ int32_t prow[kPeakBuf], pmem[kPeakBuf];
+  __shared__ float psnr[kPeakBuf];
+  __shared__ double pthr[kPeakBuf];
+  __shared__ int npk, pbase;
   const int s = blockIdx.x / a.num_widths, w = blockIdx.x - s * a.num_widths;
   const PeakFitDev f = a.fits[blockIdx.x];
   if (!f.ok) return;
@@ -326,21 +430,34 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
   const double* nu = a.nu + sd.freq0;
   const double* lx = a.lognu + sd.freq0;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) npk = 0;
   // cluster state, held by thread 0
   bool have = false;
   double nu_prev = 0.0, best_thr = 0.0;
-  int64_t best_row = 0;
+  int32_t best_row = 0;
   float best = 0.0f;
   int members = 0;
+  auto finish = [&]() {  // thread 0: the current cluster is complete
+    if (npk < kPeakBuf) {
+      prow[npk] = best_row;
+      psnr[npk] = best;
+      pthr[npk] = best_thr;
+      pmem[npk] = members;
+      ++npk;
+    } else {
+      emit_peak(a, s, w, best_row, best, best_thr, members);
+    }
+  };
   for (int64_t base = 0; base < sd.rows; base += kChunkRows) {
     // row base + q * kPeakThreads + tid of the chunk, q = 0 .. kScanRows - 1
     float v[kScanRows];
-    double x[kScanRows];
+    double x[kScanRows], fq[kScanRows];
 #pragma unroll
     for (int q = 0; q < kScanRows; ++q) {
       const int64_t r = base + q * kPeakThreads + tid;
       v[q] = r < sd.rows ? col[r * a.num_widths] : 0.0f;
       x[q] = r < sd.rows ? lx[r] : 0.0;
+      fq[q] = r < sd.rows ? nu[r] : 0.0;
     }
     bool flag[kScanRows];
     double thr[kScanRows];
@@ -349,8 +466,11 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
     for (int q = 0; q < kScanRows; ++q) {
       const int64_t r = base + q * kPeakThreads + tid;
       const double u = (x[q] - f.xbar) * f.inv_scale;
-      double t = f.c[a.degree];
-      for (int j = a.degree - 1; j >= 0; --j) t = t * u + f.c[j];
+      // coefficients past the degree are zero, so the full-degree Horner
+      // form gives the degree-d value exactly
+      double t = f.c[kPeakMaxDegree];
+#pragma unroll
+      for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
       thr[q] = t;
       flag[q] = r < sd.rows && (double)v[q] > t;  // false for a NaN S/N
       const unsigned long long m = __ballot(flag[q]);
@@ -369,50 +489,81 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
         tot += wcount[q][z];
       }
       if (flag[q]) {
-        lrow[off + before[q]] = base + q * kPeakThreads + tid;
+        lrow[off + before[q]] = (int32_t)(base + q * kPeakThreads + tid);
         lsnr[off + before[q]] = v[q];
         lthr[off + before[q]] = thr[q];
+        lnu[off + before[q]] = fq[q];
       }
     }
     __syncthreads();
     if (tid == 0) {
       for (int q = 0; q < tot; ++q) {
-        const int64_t rr = lrow[q];
-        const double fr = nu[rr];
+        const double fr = lnu[q];
         if (have && nu_prev - fr > sd.gap) {
-          emit_peak(a, s, w, best_row, best, best_thr, members);
+          finish();
           have = false;
         }
         if (!have) {
           have = true;
           members = 0;
           best = lsnr[q];
-          best_row = rr;
+          best_row = lrow[q];
           best_thr = lthr[q];
         } else if (lsnr[q] > best) {  // the first of equal S/N stays
           best = lsnr[q];
-          best_row = rr;
+          best_row = lrow[q];
           best_thr = lthr[q];
         }
         ++members;
         nu_prev = fr;
       }
+      if (have && base + kChunkRows >= sd.rows) finish();  // the last cluster
+    }
+    __syncthreads();
+    // write the buffered peaks out together when the buffer is half full
+    // and at the end
+    const int n_out = npk;
+    if (n_out > 0 && (n_out >= kPeakBuf / 2 || base + kChunkRows >= sd.rows)) {
+      if (tid == 0) {
+        pbase = atomicAdd(&a.count[0], n_out);
+        atomicAdd(&a.count[1 + s], n_out);
+      }
+      __syncthreads();
+      for (int i = tid; i < n_out; i += kPeakThreads) {
+        if (pbase + (int64_t)i < a.capacity) {
+          PeakDev pk;
+          pk.row = prow[i];
+          pk.threshold = pthr[i];
+          pk.snr = psnr[i];
+          pk.series = s;
+          pk.width = w;
+          pk.members = pmem[i];
+          pk.pad = 0;
+          a.peaks[pbase + i] = pk;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) npk = 0;
     }
     __syncthreads();  // the lists are rewritten by the next chunk
   }
-  if (tid == 0 && have) emit_peak(a, s, w, best_row, best, best_thr, members);
 }
 
 }  // namespace
 
-hipError_t launch_peak_ctrl(const PeakArgs& a, int32_t max_seg, hipStream_t stream) {
+hipError_t launch_peak_ctrl(const PeakArgs& a, hipStream_t stream) {
   if (a.nseries <= 0 || a.max_nseg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_peak_ctrl_wave, dim3(a.nseries * a.max_nseg, a.num_widths), dim3(64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || max_seg <= kWaveSortMax) return e;
-  hipLaunchKernelGGL(k_peak_ctrl, dim3(a.nseries * a.max_nseg, a.num_widths), dim3(kPeakThreads),
-                     0, stream, a);
+  if (e != hipSuccess) return e;
+  if (a.nmid > 0) {
+    hipLaunchKernelGGL(k_peak_ctrl_pair, dim3(a.nmid, a.num_widths), dim3(128), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.nbig <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_peak_ctrl, dim3(a.nbig, a.num_widths), dim3(kPeakThreads), 0, stream, a);
   return hipGetLastError();
 }
 

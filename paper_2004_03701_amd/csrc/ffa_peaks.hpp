@@ -7,6 +7,7 @@
 namespace ffa {
 
 constexpr int kPeakSegMax = 8192;   // most rows of one frequency segment (LDS sort)
+constexpr int kPeakWaveSortMax = 1024;  // most rows a segment sorted in registers holds
 constexpr int kPeakMaxDegree = 4;   // highest polynomial degree of the threshold
 constexpr int kPeakThreads = 256;
 
@@ -47,6 +48,9 @@ struct PeakArgs {
   const int32_t* seg_begin;  // first row (within the series) of every plan segment
   const int32_t* seg_end;    // one past its last row
   const double* seg_x;       // log of the segment's centre frequency
+  const int32_t* mid;        // (series, segment) pairs of segments of 1025 .. 2048 rows
+  const int32_t* big;        // and of more than 2048 rows
+  int32_t nmid, nbig;
   double* ctrl;            // control values, ((series * num_widths) + w) * max_nseg + i
   PeakFitDev* fits;        // series * num_widths + w
   PeakDev* peaks;          // capacity records
@@ -57,9 +61,9 @@ struct PeakArgs {
 // Control points of every (series, segment, width), then the least-squares
 // threshold of every (series, width), then the scan that selects and
 // clusters the points above it. count must hold 1 + nseries zeros.
-// max_seg: rows of the largest segment (segments above 1024 rows take a
-// second, LDS-sorting launch).
-hipError_t launch_peak_ctrl(const PeakArgs& a, int32_t max_seg, hipStream_t stream);
+// Segments above kPeakWaveSortMax rows (the a.nmid pairs of a.mid, up to
+// twice that, and the a.nbig pairs of a.big) take further launches.
+hipError_t launch_peak_ctrl(const PeakArgs& a, hipStream_t stream);
 hipError_t launch_peak_fit(const PeakArgs& a, hipStream_t stream);
 hipError_t launch_peak_scan(const PeakArgs& a, hipStream_t stream);
 

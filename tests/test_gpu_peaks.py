@@ -125,10 +125,10 @@ def test_peaks_of_constructed_periodograms(ctx):
     assert np.max(np.abs(np.polynomial.polynomial.polyval(x, poly[1, 0]) - want)) < 1e-4
 
 
-@pytest.mark.parametrize("dz_seg", [10.0, 30.0])
-def test_peaks_with_segments_sorted_in_lds(ctx, dz_seg):
-    # segments of more than 1024 rows take the workgroup (LDS) sort, smaller
-    # ones (the partial last segment) the register sort
+@pytest.mark.parametrize("dz_seg", [6.0, 10.0, 30.0])
+def test_peaks_with_larger_segments(ctx, dz_seg):
+    # segments of 1025 .. 2048 rows take the two-wave sort, larger ones the
+    # workgroup (LDS) sort, smaller ones the one-wave register sort
     prm = small_params()
     n = 1 << 18
     per = oracle_periods(prm, n)
