@@ -151,7 +151,7 @@ struct ffa_ctx {
   DevBuf counters, ticket;              // persistent scheduler state
   std::map<std::string, std::shared_ptr<PeakPlan>> peak_plans;
   DevBuf pk_series, pk_nu, pk_lognu, pk_segb, pk_sege, pk_segx, pk_mid, pk_big;  // peak-detection tables
-  DevBuf pk_ctrl, pk_fits, pk_peaks, pk_count;                    // and workspace
+  DevBuf pk_ctrl, pk_fits, pk_flags, pk_peaks, pk_count;          // and workspace
   std::string pk_key;    // batch the peak-detection tables were uploaded for
   int32_t pk_max_nseg = 0, pk_max_seg = 0, pk_nmid = 0, pk_nbig = 0;
   int num_cus = 256;
@@ -1171,6 +1171,10 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
   }
   const int32_t max_nseg = ctx->pk_max_nseg;
   const size_t nfit = (size_t)nseries * nw;
+  int64_t max_rows = 0;
+  for (int32_t i = 0; i < nseries; ++i) max_rows = std::max(max_rows, plans[i]->rows);
+  const int64_t nwords = (max_rows + 63) / 64;
+  HIP_TRY(ctx, ctx->pk_flags.reserve(std::max<size_t>(nfit * nwords * 8, 16)), "peak flags");
   HIP_TRY(ctx, ctx->pk_ctrl.reserve(std::max<size_t>(nfit * std::max(max_nseg, 1) * 8, 16)),
           "peak control points");
   HIP_TRY(ctx, ctx->pk_fits.reserve(nfit * sizeof(PeakFitDev)), "peak fits");
@@ -1199,6 +1203,8 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
   a.nbig = ctx->pk_nbig;
   a.ctrl = ctx->pk_ctrl.as<double>();
   a.fits = ctx->pk_fits.as<PeakFitDev>();
+  a.flags = ctx->pk_flags.as<uint64_t>();
+  a.nwords = nwords;
   a.peaks = ctx->pk_peaks.as<PeakDev>();
   a.capacity = capacity_peaks;
   a.count = ctx->pk_count.as<int32_t>();

@@ -6,9 +6,10 @@
 // selection threshold, and the points above it are clustered into peaks.
 //
 // Three steps:
-//   k_peak_ctrl_wave / k_peak_ctrl_pair / k_peak_ctrl
+//   k_peak_ctrl_seg (k_peak_ctrl_wave) / k_peak_ctrl_pair / k_peak_ctrl
 //                the control points: one wave (segments of up to 1024 rows,
-//                sorted in registers), two waves (up to 2048 rows, one stage
+//                sorted in registers; one workgroup takes every width of a
+//                segment when there are at most 12), two waves (up to 2048 rows, one stage
 //                through LDS) or one workgroup (larger segments, sorted in
 //                LDS) per (series, segment, width) sorts the segment's S/N
 //                values with a bitonic network and reads the quantiles from
@@ -16,9 +17,11 @@
 //   k_peak_fit   one wave per (series, width): power sums of the control
 //                points on a centred and scaled abscissa, reduced across the
 //                wave, and the normal equations solved in FP64;
-//   k_peak_scan  one workgroup per (series, width): every row's threshold,
-//                the rows above it compacted in row (= frequency) order and
-//                walked by one thread that forms the clusters.
+//   k_peak_flag / k_peak_cluster
+//                every row's thresholds, the rows above them as one bit per
+//                (row, width) from wave ballots; then one wave per (series,
+//                width) lists the set rows in row (= frequency) order and
+//                one lane walks them forming the clusters.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -109,7 +112,10 @@ __device__ __forceinline__ void bitonic_stage(float (&v)[16], int lane, int e0) 
     for (int r = 0; r < 16; ++r) {
       const bool up = ((e0 + lane * 16 + r) & K) == 0;
       const float x = v[r], y = from_lane_xor<D>(x, lane);
-      v[r] = (lower == up) ? fminf(x, y) : fmaxf(x, y);
+      // the lower element of an ascending block keeps the minimum (values
+      // are finite or +inf, so a compare and a select do it)
+      const bool sw = (x > y) == (lower == up);
+      v[r] = sw ? y : x;
     }
   }
 }
@@ -178,6 +184,52 @@ __global__ __launch_bounds__(64) void k_peak_ctrl_wave(PeakArgs a) {
     v[r] = x;
   }
   if (__ballot(bad)) {
+    if (lane == 0) *out = NAN;
+    return;
+  }
+  bitonic_sort<2>(v, lane, 0);
+  const double med = wave_quantile(v, n, 0.5);
+  const double iqr = wave_quantile(v, n, 0.75) - wave_quantile(v, n, 0.25);
+  if (lane == 0) *out = med + a.k_sigma * iqr / 1.349;
+}
+
+// The same for every width of a segment at once (num_widths <= kSegWidths):
+// the workgroup copies the segment's rows (contiguous, all widths) to LDS in
+// one coalesced pass and wave w sorts width w from there.
+constexpr int kSegWidths = 12;
+
+__global__ __launch_bounds__(64 * kSegWidths) void k_peak_ctrl_seg(PeakArgs a) {
+  extern __shared__ float seg[];  // n x num_widths
+  const int s = blockIdx.x / a.max_nseg, i = blockIdx.x - s * a.max_nseg;
+  const int nw = a.num_widths, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const PeakSeriesDev sd = a.series[s];
+  if (i >= sd.nseg) return;
+  const int rb = a.seg_begin[sd.seg0 + i], n = a.seg_end[sd.seg0 + i] - rb;
+  if (n > kWaveSortMax) return;  // the two-wave and LDS forms take it
+  double* out = a.ctrl + ((int64_t)s * nw + w) * a.max_nseg + i;
+  if (n < a.min_points) {
+    if (lane == 0) *out = NAN;
+    return;
+  }
+  const float* src = a.snr + (sd.snr_row0 + rb) * nw;
+  for (int q = threadIdx.x; q < n * nw; q += blockDim.x) seg[q] = src[q];
+  __syncthreads();
+  float v[16];
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int e = r * 64 + lane;
+    float x = INFINITY;
+    if (e < n) {
+      x = seg[e * nw + w];
+      if (!isfinite(x)) {
+        bad = true;
+        x = INFINITY;
+      }
+    }
+    v[r] = x;
+  }
+  if (__ballot(bad)) {  // per wave: no barrier follows
     if (lane == 0) *out = NAN;
     return;
   }
@@ -405,39 +457,106 @@ __device__ __forceinline__ void emit_peak(const PeakArgs& a, int s, int w, int64
   }
 }
 
-// Rows per thread and chunk of the scan: their loads are issued together.
-constexpr int kScanRows = 4;
-// Finished peaks a scan workgroup holds before writing them out together.
+// Selection: every row's thresholds and the rows above them, as one bit per
+// (row, width). A workgroup takes kFlagRows consecutive rows of one series;
+// a wave reads 64 whole rows (every width, coalesced) per step and one
+// ballot per width gives the 64 bits of that width.
+constexpr int kFlagRows = 4096;
+
+__global__ __launch_bounds__(kPeakThreads) void k_peak_flag(PeakArgs a) {
+  constexpr int kMaxW = 32;
+  __shared__ PeakFitDev fit[kMaxW];
+  const int nw = a.num_widths;
+  const int chunks = (int)((a.nwords * 64 + kFlagRows - 1) / kFlagRows);
+  const int s = blockIdx.x / chunks, c = blockIdx.x - s * chunks;
+  const PeakSeriesDev sd = a.series[s];
+  const int64_t r0 = (int64_t)c * kFlagRows;
+  if (r0 >= sd.rows) return;
+  if (threadIdx.x < nw) fit[threadIdx.x] = a.fits[(int64_t)s * nw + threadIdx.x];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float* snr = a.snr + sd.snr_row0 * nw;
+  const double* lx = a.lognu + sd.freq0;
+  uint64_t* bits = a.flags + (int64_t)s * nw * a.nwords;
+  constexpr int kG = 16;  // widths loaded together
+  for (int64_t rb = r0 + wave * 64; rb < r0 + kFlagRows && rb < sd.rows; rb += kPeakThreads) {
+    const int64_t r = rb + lane;
+    const bool in = r < sd.rows;
+    const double x = in ? lx[r] : 0.0;
+    for (int w0 = 0; w0 < nw; w0 += kG) {
+      float v[kG];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) v[g] = (in && w0 + g < nw) ? snr[r * nw + w0 + g] : 0.0f;
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int w = w0 + g;
+        if (w >= nw) break;  // uniform
+        const PeakFitDev& f = fit[w];
+        const double u = (x - f.xbar) * f.inv_scale;
+        // coefficients past the degree are zero, so the full-degree Horner
+        // form gives the degree-d value exactly
+        double t = f.c[kPeakMaxDegree];
+#pragma unroll
+        for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
+        const bool flag = in && f.ok && (double)v[g] > t;  // false for a NaN S/N
+        const unsigned long long m = __ballot(flag);
+        if (lane == 0) bits[(int64_t)w * a.nwords + (rb >> 6)] = m;
+      }
+    }
+  }
+}
+
+// Clustering: one wave per (series, width) reads the width's bits 64 words
+// at a time, lists the set rows in order, gathers their S/N, threshold and
+// frequency 64 rows at a time, and lane 0 walks them forming the clusters.
+// Finished peaks are buffered and written out together.
 constexpr int kPeakBuf = 128;
 
-__global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
-  constexpr int kWaves = kPeakThreads / 64, kChunkRows = kScanRows * kPeakThreads;
-  // rows above the threshold in the current chunk, in row order
-  __shared__ int32_t lrow[kChunkRows];
-  __shared__ float lsnr[kChunkRows];
-  __shared__ double lthr[kChunkRows], lnu[kChunkRows];
-  __shared__ int wcount[kScanRows][kWaves];
-  // finished peaks not yet written
+__global__ __launch_bounds__(64) void k_peak_cluster(PeakArgs a) {
+  __shared__ int32_t list[64 * 64];
+  __shared__ float bsnr[64];
+  __shared__ double bthr[64], bnu[64];
   __shared__ int32_t prow[kPeakBuf], pmem[kPeakBuf];
   __shared__ float psnr[kPeakBuf];
   __shared__ double pthr[kPeakBuf];
-  __shared__ int npk, pbase;
-  const int s = blockIdx.x / a.num_widths, w = blockIdx.x - s * a.num_widths;
+  const int nw = a.num_widths;
+  const int s = blockIdx.x / nw, w = blockIdx.x - s * nw;
+  const int lane = threadIdx.x;
   const PeakFitDev f = a.fits[blockIdx.x];
   if (!f.ok) return;
   const PeakSeriesDev sd = a.series[s];
-  const float* col = a.snr + sd.snr_row0 * a.num_widths + w;
-  const double* nu = a.nu + sd.freq0;
+  const uint64_t* bits = a.flags + ((int64_t)s * nw + w) * a.nwords;
+  const int nwords = (int)((sd.rows + 63) >> 6);
+  const float* snr = a.snr + sd.snr_row0 * nw + w;
   const double* lx = a.lognu + sd.freq0;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) npk = 0;
-  // cluster state, held by thread 0
+  const double* nu = a.nu + sd.freq0;
+  // cluster state and the count of buffered peaks, held by lane 0
   bool have = false;
   double nu_prev = 0.0, best_thr = 0.0;
   int32_t best_row = 0;
   float best = 0.0f;
-  int members = 0;
-  auto finish = [&]() {  // thread 0: the current cluster is complete
+  int members = 0, npk = 0;
+  auto flush = [&](int n_out) {  // every lane: write buffered peaks 0 .. n_out - 1
+    int base = 0;
+    if (lane == 0) {
+      base = atomicAdd(&a.count[0], n_out);
+      atomicAdd(&a.count[1 + s], n_out);
+    }
+    base = __shfl(base, 0, 64);
+    for (int q = lane; q < n_out; q += 64)
+      if (base + (int64_t)q < a.capacity) {
+        PeakDev pk;
+        pk.row = prow[q];
+        pk.threshold = pthr[q];
+        pk.snr = psnr[q];
+        pk.series = s;
+        pk.width = w;
+        pk.members = pmem[q];
+        pk.pad = 0;
+        a.peaks[base + q] = pk;
+      }
+  };
+  auto finish = [&]() {  // lane 0: the current cluster is complete
     if (npk < kPeakBuf) {
       prow[npk] = best_row;
       psnr[npk] = best;
@@ -448,113 +567,82 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_scan(PeakArgs a) {
       emit_peak(a, s, w, best_row, best, best_thr, members);
     }
   };
-  for (int64_t base = 0; base < sd.rows; base += kChunkRows) {
-    // row base + q * kPeakThreads + tid of the chunk, q = 0 .. kScanRows - 1
-    float v[kScanRows];
-    double x[kScanRows], fq[kScanRows];
+  for (int w0 = 0; w0 < nwords; w0 += 64) {
+    const int wi = w0 + lane;
+    const uint64_t m = wi < nwords ? bits[wi] : 0ull;
+    const int cnt = __popcll(m);
+    int pre = cnt;  // inclusive prefix over lanes
 #pragma unroll
-    for (int q = 0; q < kScanRows; ++q) {
-      const int64_t r = base + q * kPeakThreads + tid;
-      v[q] = r < sd.rows ? col[r * a.num_widths] : 0.0f;
-      x[q] = r < sd.rows ? lx[r] : 0.0;
-      fq[q] = r < sd.rows ? nu[r] : 0.0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(pre, o, 64);
+      if (lane >= o) pre += t;
     }
-    bool flag[kScanRows];
-    double thr[kScanRows];
-    int before[kScanRows];
-#pragma unroll
-    for (int q = 0; q < kScanRows; ++q) {
-      const int64_t r = base + q * kPeakThreads + tid;
-      const double u = (x[q] - f.xbar) * f.inv_scale;
-      // coefficients past the degree are zero, so the full-degree Horner
-      // form gives the degree-d value exactly
-      double t = f.c[kPeakMaxDegree];
-#pragma unroll
-      for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
-      thr[q] = t;
-      flag[q] = r < sd.rows && (double)v[q] > t;  // false for a NaN S/N
-      const unsigned long long m = __ballot(flag[q]);
-      before[q] = __popcll(m & ((1ull << lane) - 1ull));
-      if (lane == 0) wcount[q][wave] = __popcll(m);
-    }
+    const int total = __shfl(pre, 63, 64);
+    if (total == 0) continue;
+    int pos = pre - cnt;
+    for (uint64_t mm = m; mm; mm &= mm - 1) list[pos++] = wi * 64 + __builtin_ctzll(mm);
     __syncthreads();
-    // compaction in row order: sub-chunk q, then wave, then lane
-    int tot = 0;
+    for (int b0 = 0; b0 < total; b0 += 64) {
+      const int k = b0 + lane;
+      if (k < total) {
+        const int32_t r = list[k];
+        const double u = (lx[r] - f.xbar) * f.inv_scale;
+        double t = f.c[kPeakMaxDegree];
 #pragma unroll
-    for (int q = 0; q < kScanRows; ++q) {
-      int off = tot;
-#pragma unroll
-      for (int z = 0; z < kWaves; ++z) {
-        off += z < wave ? wcount[q][z] : 0;
-        tot += wcount[q][z];
-      }
-      if (flag[q]) {
-        lrow[off + before[q]] = (int32_t)(base + q * kPeakThreads + tid);
-        lsnr[off + before[q]] = v[q];
-        lthr[off + before[q]] = thr[q];
-        lnu[off + before[q]] = fq[q];
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int q = 0; q < tot; ++q) {
-        const double fr = lnu[q];
-        if (have && nu_prev - fr > sd.gap) {
-          finish();
-          have = false;
-        }
-        if (!have) {
-          have = true;
-          members = 0;
-          best = lsnr[q];
-          best_row = lrow[q];
-          best_thr = lthr[q];
-        } else if (lsnr[q] > best) {  // the first of equal S/N stays
-          best = lsnr[q];
-          best_row = lrow[q];
-          best_thr = lthr[q];
-        }
-        ++members;
-        nu_prev = fr;
-      }
-      if (have && base + kChunkRows >= sd.rows) finish();  // the last cluster
-    }
-    __syncthreads();
-    // write the buffered peaks out together when the buffer is half full
-    // and at the end
-    const int n_out = npk;
-    if (n_out > 0 && (n_out >= kPeakBuf / 2 || base + kChunkRows >= sd.rows)) {
-      if (tid == 0) {
-        pbase = atomicAdd(&a.count[0], n_out);
-        atomicAdd(&a.count[1 + s], n_out);
+        for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
+        bsnr[lane] = snr[(int64_t)r * nw];
+        bthr[lane] = t;
+        bnu[lane] = nu[r];
       }
       __syncthreads();
-      for (int i = tid; i < n_out; i += kPeakThreads) {
-        if (pbase + (int64_t)i < a.capacity) {
-          PeakDev pk;
-          pk.row = prow[i];
-          pk.threshold = pthr[i];
-          pk.snr = psnr[i];
-          pk.series = s;
-          pk.width = w;
-          pk.members = pmem[i];
-          pk.pad = 0;
-          a.peaks[pbase + i] = pk;
+      if (lane == 0) {
+        const int nb = total - b0 < 64 ? total - b0 : 64;
+        for (int q = 0; q < nb; ++q) {
+          const double fr = bnu[q];
+          if (have && nu_prev - fr > sd.gap) {
+            finish();
+            have = false;
+          }
+          if (!have) {
+            have = true;
+            members = 0;
+            best = bsnr[q];
+            best_row = list[b0 + q];
+            best_thr = bthr[q];
+          } else if (bsnr[q] > best) {  // the first of equal S/N stays
+            best = bsnr[q];
+            best_row = list[b0 + q];
+            best_thr = bthr[q];
+          }
+          ++members;
+          nu_prev = fr;
         }
       }
       __syncthreads();
-      if (tid == 0) npk = 0;
     }
-    __syncthreads();  // the lists are rewritten by the next chunk
+    const int n_out = __shfl(npk, 0, 64);
+    if (n_out >= kPeakBuf / 2) {
+      flush(n_out);
+      npk = 0;
+      __syncthreads();
+    }
   }
+  if (lane == 0 && have) finish();  // the last cluster
+  __syncthreads();
+  const int n_out = __shfl(npk, 0, 64);
+  if (n_out > 0) flush(n_out);
 }
 
 }  // namespace
 
 hipError_t launch_peak_ctrl(const PeakArgs& a, hipStream_t stream) {
   if (a.nseries <= 0 || a.max_nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_peak_ctrl_wave, dim3(a.nseries * a.max_nseg, a.num_widths), dim3(64), 0,
-                     stream, a);
+  if (a.num_widths <= kSegWidths)
+    hipLaunchKernelGGL(k_peak_ctrl_seg, dim3(a.nseries * a.max_nseg), dim3(64 * a.num_widths),
+                       kWaveSortMax * a.num_widths * sizeof(float), stream, a);
+  else
+    hipLaunchKernelGGL(k_peak_ctrl_wave, dim3(a.nseries * a.max_nseg, a.num_widths), dim3(64), 0,
+                       stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.nmid > 0) {
@@ -574,9 +662,12 @@ hipError_t launch_peak_fit(const PeakArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_peak_scan(const PeakArgs& a, hipStream_t stream) {
-  if (a.nseries <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_peak_scan, dim3(a.nseries * a.num_widths), dim3(kPeakThreads), 0, stream,
-                     a);
+  if (a.nseries <= 0 || a.nwords <= 0) return hipSuccess;
+  const int chunks = (int)((a.nwords * 64 + kFlagRows - 1) / kFlagRows);
+  hipLaunchKernelGGL(k_peak_flag, dim3(a.nseries * chunks), dim3(kPeakThreads), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_peak_cluster, dim3(a.nseries * a.num_widths), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -53,14 +53,16 @@ struct PeakArgs {
   int32_t nmid, nbig;
   double* ctrl;            // control values, ((series * num_widths) + w) * max_nseg + i
   PeakFitDev* fits;        // series * num_widths + w
+  uint64_t* flags;         // rows above the threshold, ((series * num_widths) + w) * nwords words
+  int64_t nwords;          // 64-row words per (series, width): rows of the longest series / 64
   PeakDev* peaks;          // capacity records
   int64_t capacity;
   int32_t* count;          // [0]: peaks found; [1 + s]: peaks of series s
 };
 
 // Control points of every (series, segment, width), then the least-squares
-// threshold of every (series, width), then the scan that selects and
-// clusters the points above it. count must hold 1 + nseries zeros.
+// threshold of every (series, width), then the selection of the points above
+// it (flags) and their clustering. count must hold 1 + nseries zeros.
 // Segments above kPeakWaveSortMax rows (the a.nmid pairs of a.mid, up to
 // twice that, and the a.nbig pairs of a.big) take further launches.
 hipError_t launch_peak_ctrl(const PeakArgs& a, hipStream_t stream);
