@@ -157,9 +157,10 @@ def copy_ceiling(torch, mib=1024, reps=10):
 
 
 def bench_peaks(ffa, ctx, snr, prm, nsamp, rows1, a):
-    """Peak detection of every series' periodogram, timed per kernel with HIP
-    events (three launches per call) and by wall clock (the call includes its
-    host work and the copy of the peaks to the host)."""
+    """Peak detection of every series' periodogram, timed with HIP events
+    around its three steps (control points, fit, selection and clustering)
+    and by wall clock (the call includes its host work and the copy of the
+    peaks to the host)."""
     import torch
     n = len(prm)
     ro = [i * rows1 for i in range(n)]
@@ -181,7 +182,7 @@ def bench_peaks(ffa, ctx, snr, prm, nsamp, rows1, a):
     alg = 2 * snr.shape[0] * snr.shape[1] * 4 + 16 * rows1
     gbs = alg / (kms * 1e-3) / 1e9
     return {"ms_per_call": 1e3 * wall, "kernel_ms": kms,
-            "launches_per_call": tm["peaks_launches"] / a.steps, "alg_bytes": alg,
+            "timed_steps_per_call": tm["peaks_launches"] / a.steps, "alg_bytes": alg,
             "alg_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS, "peaks_found": int(counts.sum()),
             "params": {"dz_seg": pp.dz_seg, "k_sigma": pp.k_sigma, "degree": pp.degree,
                        "min_points": pp.min_points, "cluster_gap": pp.cluster_gap}}

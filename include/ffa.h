@@ -261,7 +261,7 @@ typedef struct {
   int64_t input_samples;       /* raw samples read */
   int64_t downsampled_samples; /* samples written by the downsampler */
   double peaks_ms;             /* peak-detection kernels (Sec. 5.5) */
-  int64_t peaks_launches;
+  int64_t peaks_launches;      /* timed peak-detection steps: control points, fit, selection */
 } ffa_kernel_times;
 
 /* Turns per-kernel timing on (1) or off (0) for the calls that follow. */

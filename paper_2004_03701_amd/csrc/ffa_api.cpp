@@ -1254,13 +1254,19 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
   for (int64_t q = 0; q < total; ++q) {
     const PeakDev& d = pk[q];
     const SeriesPlan& plan = *plans[d.series];
-    // period of the row from the plan (the same formula as ffa_plan_export)
+    // period of the row from the plan (the same formula as ffa_plan_export);
+    // transforms are in row order, so the row's transform is the last one
+    // starting at or before it that keeps rows
     double period = NAN;
-    for (const Transform& t : plan.tr)
-      if (d.row >= t.row0 && d.row < t.row0 + t.keep) {
+    auto it = std::upper_bound(plan.tr.begin(), plan.tr.end(), d.row,
+                               [](int64_t row, const Transform& t) { return row < t.row0; });
+    while (it != plan.tr.begin()) {
+      const Transform& t = *--it;
+      if (t.keep == 0) continue;
+      if (d.row < t.row0 + t.keep)
         period = trial_period(d.row - t.row0, t.m, t.p, plan.oct[t.octave].tau);
-        break;
-      }
+      break;
+    }
     ffa_peak& o = peaks_host[q];
     o.row = d.row;
     o.period = period;
