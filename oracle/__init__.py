@@ -298,3 +298,21 @@ def search(x: np.ndarray, tsamp: float, period_min: float, period_max: float, bi
                        snr=np.concatenate(snr_l) if snr_l else np.zeros((0, w.size)),
                        octave=cat(oct_l, np.int32), rows_m=cat(m_l, np.int32),
                        s=cat(s_l, np.int32))
+
+
+def search_ranges(x: np.ndarray, tsamp: float, ranges, widths: Sequence[int],
+                  normalise: bool = True) -> Periodogram:
+    """Dynamic duty-cycle resolution (Sec. 5.6): the period range cut into
+    consecutive sub-ranges, each searched with its own (period_min,
+    period_max, bins_min, bins_max), and the periodograms concatenated in
+    range order. `ranges` holds those four values per sub-range, ascending and
+    without overlap."""
+    parts = []
+    for k, (pmin, pmax, bmin, bmax) in enumerate(ranges):
+        if k > 0 and ranges[k - 1][1] > pmin:
+            raise PlanError("sub-ranges must ascend without overlap")
+        parts.append(search(x, tsamp, pmin, pmax, bmin, bmax, widths, normalise=normalise))
+    cat = lambda f: np.concatenate([getattr(q, f) for q in parts])
+    return Periodogram(periods=cat("periods"), bins=cat("bins"),
+                       snr=np.concatenate([q.snr for q in parts]), octave=cat("octave"),
+                       rows_m=cat("rows_m"), s=cat("s"))

@@ -386,3 +386,39 @@ def test_tie_reading_is_half_up():
     assert oracle.path_offset(5, 2, 0) == 0
     assert oracle.path_offset(5, 2, 1) == 1   # head row 1 reached through H_1
     assert oracle.path_offset(5, 2, 2) == 1   # first tail row: rotation s - j = 1
+
+
+# --------------------------------------------------------------------------
+# Dynamic duty-cycle resolution (Sec. 5.6)
+# --------------------------------------------------------------------------
+
+def test_sub_ranges_resolve_a_narrow_pulse_better():
+    # Sec. 5.6: more phase bins at longer periods raise the duty-cycle
+    # resolution there. A 2-sample boxcar pulse at period 700.37 samples is
+    # smeared over 4-sample bins with 128..255 bins per profile; a second
+    # sub-range [256, 1024) with 256..511 bins has 2-sample bins there, so its
+    # best S/N near the pulse period is clearly higher (16.7 against 12.3 for
+    # an amplitude of 25; the rest is lost to the 1-bin phase and drift steps).
+    n = 1 << 18
+    period, a = 700.37, 25.0
+    t = np.arange(n, dtype=np.float64)
+    ph = np.mod(t / period, 1.0) * period
+    s = ((ph >= 100.0) & (ph < 102.0)).astype(np.float64)
+    s /= np.sqrt(np.sum(s * s))
+    x = a * s + 1e-3 * rng(61).standard_normal(n)
+    widths = (1, 2, 3, 4)
+    coarse = oracle.search(x, 1.0, 128.0, 1024.0, 128, 255, widths, normalise=False)
+    fine = oracle.search_ranges(x, 1.0, [(128.0, 256.0, 128, 255), (256.0, 1024.0, 256, 511)],
+                                widths, normalise=False)
+    # the concatenation: ascending periods inside [128, 1024), each part its own search
+    assert np.all(np.diff(fine.periods) > 0)
+    assert fine.periods[0] >= 128.0 and fine.periods[-1] < 1024.0
+    first = oracle.search(x, 1.0, 128.0, 256.0, 128, 255, widths, normalise=False)
+    k = first.periods.size
+    assert np.array_equal(fine.snr[:k], first.snr) and np.all(fine.periods[k:] >= 256.0)
+    near = lambda pg: pg.snr[np.abs(pg.periods - period) < 1.0].max()
+    assert near(fine) > near(coarse) + 3.0
+    assert near(fine) > 0.6 * a
+    with pytest.raises(oracle.PlanError):
+        oracle.search_ranges(x, 1.0, [(128.0, 300.0, 128, 255), (256.0, 1024.0, 256, 511)],
+                             widths, normalise=False)
