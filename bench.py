@@ -49,6 +49,9 @@ def parse():
                     help="1: after the per-kernel timed steps, time the same steps again as "
                          "hipGraph replays (the headline value); 0: eager launches only")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--ranges", type=int, default=64,
+                    help="series of the dynamic duty-cycle leg (Sec. 5.6): 0.5-2 s at 240-259 "
+                         "bins and 2-10 s at 480-519 bins, FP32; 0 skips it")
     ap.add_argument("--peaks", type=int, default=1,
                     help="1: also time peak detection (Sec. 5.5) on the headline variant's "
                          "periodograms, reported apart from the step")
@@ -186,6 +189,38 @@ def bench_peaks(ffa, ctx, snr, prm, nsamp, rows1, a):
             "alg_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS, "peaks_found": int(counts.sum()),
             "params": {"dz_seg": pp.dz_seg, "k_sigma": pp.k_sigma, "degree": pp.degree,
                        "min_points": pp.min_points, "cluster_gap": pp.cluster_gap}}
+
+
+def bench_ranges(ffa, ctx, x32, nsamp, cfg, a):
+    """Dynamic duty-cycle resolution (Sec. 5.6) on the first a.ranges series:
+    every series searched over two sub-ranges in one batch (each series an
+    entry per sub-range), against the same series searched over 0.5-10 s at
+    240-259 bins."""
+    import torch
+    n = min(a.ranges, x32.shape[0])
+    series = [x32[i] for i in range(n)]
+    sub = [(0.5, 2.0, 240, 259), (2.0, 10.0, 480, 519)]
+    out = {"series": n, "ranges_s_bins": [list(r) for r in sub]}
+    for name, rng in (("sub_ranges", sub), ("single_range", [(0.5, 10.0, 240, 259)])):
+        prm = [ffa.make_params(cfg.tsamp, lo, hi, bmin, bmax, cfg.widths)
+               for _ in range(n) for (lo, hi, bmin, bmax) in rng]
+        ser = [x for x in series for _ in rng]
+        snr, _ = ffa.ffa_search_batch(ctx, ser, prm)
+        torch.cuda.synchronize()
+        ffa.ffa_set_timing(ctx, True)
+        ffa.ffa_read_timing(ctx, reset=True)
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            ffa.ffa_search_batch(ctx, ser, prm, snr=snr)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / a.steps
+        tm = ffa.ffa_read_timing(ctx, reset=True)
+        ffa.ffa_set_timing(ctx, False)
+        rows = snr.shape[0]
+        out[name] = {"ms_per_step": 1e3 * wall, "profiles": rows,
+                     "profiles_per_s": rows / wall, "fold_ms": tm["fold_ms"] / a.steps}
+        del snr
+    return out
 
 
 def cpu_baseline(seconds, nsamp):
@@ -365,6 +400,7 @@ def main():
         results[v] = res
         del series, xs, snr
         torch.cuda.empty_cache()
+    ranges_res = bench_ranges(ffa, ctx, x32, nsamp, cfg, a) if a.ranges else None
     head = variants[0]
     r = results[head]
     out = {
@@ -399,6 +435,8 @@ def main():
                                    "frac": r["fold_alg_Tops"] / VALU_PEAK_TOPS}}
     if "peaks" in r:
         out["peaks"] = r["peaks"]
+    if ranges_res:
+        out["ranges"] = ranges_res
     out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk not in ("timing", "peaks")}
                        for k, v in results.items()}
     if "f32" in results and head != "f32":

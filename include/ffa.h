@@ -136,6 +136,25 @@ ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* se
                             const int64_t* row_offset, float* snr_dev, int64_t capacity_rows,
                             int32_t use_graph, void* stream);
 
+/* Dynamic duty-cycle resolution (Sec. 5.6): the period range of one series
+ * split into nranges consecutive sub-ranges, each searched with its own
+ * parameters (typically more phase bins at longer periods), the periodograms
+ * concatenated in range order.
+ *   series, nsamp  DEVICE series of nsamp samples, as ffa_search.
+ *   ranges       HOST array of nranges parameter sets with equal tsamp,
+ *                normalise, dtype and widths (so w_max < every bins_min), in
+ *                ascending period order without overlap (period_max of range k
+ *                <= period_min of range k + 1); FFA_ERR_INVALID_ARG otherwise.
+ *   period_host, bins_host  HOST or NULL, as ffa_search, over all rows.
+ *   range_row0   HOST, nranges + 1 int64 or NULL: first row of each range
+ *                and, last, the total number of rows.
+ *   snr_dev      DEVICE, capacity_rows x num_widths FP32.
+ * The series is normalised (if asked) and downsampled once per range. */
+ffa_status ffa_search_ranges(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                             const ffa_search_params* ranges, int32_t nranges,
+                             double* period_host, int32_t* bins_host, int64_t* range_row0,
+                             float* snr_dev, int64_t capacity_rows, void* stream);
+
 /* Folding transform alone (Sec. 2.1, 2.2), for parity checks: in and out are
  * DEVICE m x p FP32 arrays, row-major; row s of out is the profile folded along
  * the path that drifts s bins over the m rows. 1 <= m, 2 <= p <= 1280,

@@ -35,7 +35,7 @@ EXPORTED = (
     "ffa_create", "ffa_destroy", "ffa_status_string", "ffa_last_error", "ffa_plan_rows",
     "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
     "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
-    "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch",
+    "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch", "ffa_search_ranges",
 )
 
 
@@ -136,6 +136,7 @@ def lib() -> ctypes.CDLL:
         "ffa_autotune": ([vp, i32, P(vp), P(i64), pp, ctypes.c_char_p, P(ffa_tiling), vp], i32),
         "ffa_set_timing": ([vp, i32], i32),
         "ffa_read_timing": ([vp, P(ffa_kernel_times), i32], i32),
+        "ffa_search_ranges": ([vp, vp, i64, pp, i32, vp, vp, vp, vp, i64, vp], i32),
         "ffa_find_peaks_batch": ([vp, i32, P(i64), pp, P(i64), vp, i64, P(ffa_peak_params), vp,
                                   i64, P(i64), vp, vp], i32),
     }
@@ -264,6 +265,27 @@ def ffa_search_batch(ctx, series: Sequence, params: Sequence[ffa_search_params],
                                 1 if use_graph else 0, _stream(stream))
     _check(st, ctx)
     return snr, np.asarray(row_offset, dtype=np.int64)
+
+
+def ffa_search_ranges(ctx, series, ranges: Sequence[ffa_search_params], snr=None, stream=None):
+    """Periodogram of one device series over consecutive period sub-ranges,
+    each with its own parameters. Returns (periods, bins, snr, range_row0)."""
+    import torch
+    n = len(ranges)
+    nsamp = int(series.numel())
+    rows = [ffa_plan_rows(r, nsamp) for r in ranges]
+    total = int(sum(rows))
+    if snr is None:
+        snr = torch.empty((total, ranges[0].num_widths), dtype=torch.float32, device=series.device)
+    per = np.zeros(total, dtype=np.float64)
+    bins = np.zeros(total, dtype=np.int32)
+    row0 = np.zeros(n + 1, dtype=np.int64)
+    prm = (ffa_search_params * n)(*ranges)
+    st = lib().ffa_search_ranges(ctx, series.data_ptr(), nsamp, prm, n, per.ctypes.data,
+                                 bins.ctypes.data, row0.ctypes.data, snr.data_ptr(),
+                                 snr.shape[0], _stream(stream))
+    _check(st, ctx)
+    return per, bins, snr, row0
 
 
 def ffa_transform(ctx, x, out=None, stream=None):

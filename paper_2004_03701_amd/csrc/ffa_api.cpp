@@ -746,6 +746,49 @@ ffa_status ffa_search(ffa_ctx* ctx, const void* series, int64_t nsamp,
                    static_cast<hipStream_t>(stream));
 }
 
+ffa_status ffa_search_ranges(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                             const ffa_search_params* ranges, int32_t nranges,
+                             double* period_host, int32_t* bins_host, int64_t* range_row0,
+                             float* snr_dev, int64_t capacity_rows, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !ranges || nranges < 1 || !snr_dev)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "null series, ranges or snr pointer, or nranges < 1");
+  for (int32_t k = 0; k < nranges; ++k) {
+    const ffa_search_params& r = ranges[k];
+    if (r.tsamp != ranges[0].tsamp || r.normalise != ranges[0].normalise)
+      return fail(ctx, FFA_ERR_INVALID_ARG, "sub-ranges need the same tsamp and normalise");
+    if (k > 0 && !(ranges[k - 1].period_max <= r.period_min))
+      return fail(ctx, FFA_ERR_INVALID_ARG,
+                  "sub-ranges must be in ascending period order without overlap");
+  }
+  std::vector<int64_t> row0(nranges + 1, 0);
+  std::vector<std::shared_ptr<SeriesPlan>> plans(nranges);
+  for (int32_t k = 0; k < nranges; ++k) {
+    ffa_status st = get_plan(ctx, ranges[k], nsamp, &plans[k]);
+    if (st != FFA_OK) return st;
+    row0[k + 1] = row0[k] + plans[k]->rows;
+  }
+  if (capacity_rows < row0[nranges])
+    return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
+  if (range_row0)
+    for (int32_t k = 0; k <= nranges; ++k) range_row0[k] = row0[k];
+  if (period_host || bins_host)
+    for (int32_t k = 0; k < nranges; ++k)
+      for (const Transform& t : plans[k]->tr) {
+        const Octave& o = plans[k]->oct[t.octave];
+        for (int32_t r = 0; r < t.keep; ++r) {
+          const int64_t row = row0[k] + t.row0 + r;
+          if (period_host) period_host[row] = trial_period(r, t.m, t.p, o.tau);
+          if (bins_host) bins_host[row] = t.p;
+        }
+      }
+  // one batch whose entries are the same series with each range's parameters
+  std::vector<const void*> ptrs(nranges, series);
+  std::vector<int64_t> ns(nranges, nsamp);
+  return run_batch(ctx, nranges, ptrs.data(), ns.data(), ranges, row0.data(), snr_dev,
+                   capacity_rows, 0, static_cast<hipStream_t>(stream));
+}
+
 ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                             const int64_t* nsamp, const ffa_search_params* params,
                             const int64_t* row_offset, float* snr_dev, int64_t capacity_rows,
