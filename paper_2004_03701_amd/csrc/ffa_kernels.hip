@@ -979,7 +979,8 @@ __device__ __forceinline__ void load_rows(float* rows, int count, int p, int str
 }
 
 // load_rows for one column group per lane and FP32 rows, with `work` run
-// between the loads and the LDS stores (while the loads are in flight).
+// between the loads and the LDS stores (while the loads are in flight). It
+// reads scratch rows, each once, with non-temporal loads.
 template <int WV, class F>
 __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p, int stride,
                                                   const float* base, int64_t src, F&& work) {
@@ -999,7 +1000,7 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
       const int c = lane + 64 * k;
       int col = c < p ? c : c - p;
       if (col >= p) col %= p;
-      v[r][k] = (r < nrw && c < width) ? bits_value<FFA_F32>(load_bits<FFA_F32>(base, g + col)) : 0.0f;
+      v[r][k] = (r < nrw && c < width) ? __builtin_nontemporal_load(&((gptr<float>)base)[g + col]) : 0.0f;
     }
   }
   work();
@@ -1012,7 +1013,10 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
     }
 }
 
-// Writes rows [0, count) of LDS to global rows dst + q * p, coalesced.
+// Writes rows [0, count) of LDS to global rows dst + q * p, coalesced. The
+// stores are non-temporal: these rows (scratch between passes, or output
+// rows) are read once, by a later launch, and need not displace the
+// downsampled series that the transforms of a pseudo-octave share in L2.
 template <int WV, int JS>
 __device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
                                            float* dst) {
@@ -1034,7 +1038,7 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         const int c = lane + 64 * k;
-        if (r < nrw && c < p) dst[(int64_t)(wave + WV * r) * p + c] = v[r][k];
+        if (r < nrw && c < p) __builtin_nontemporal_store(v[r][k], &dst[(int64_t)(wave + WV * r) * p + c]);
       }
     return;
   }
@@ -1053,7 +1057,8 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int c = c0 + lane + 64 * k;
-          if (rb + u < nrw && c < p) dst[(int64_t)(wave + WV * (rb + u)) * p + c] = v[u][k];
+          if (rb + u < nrw && c < p)
+            __builtin_nontemporal_store(v[u][k], &dst[(int64_t)(wave + WV * (rb + u)) * p + c]);
         }
     }
   }

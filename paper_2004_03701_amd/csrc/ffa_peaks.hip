@@ -478,29 +478,40 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_flag(PeakArgs a) {
   const float* snr = a.snr + sd.snr_row0 * nw;
   const double* lx = a.lognu + sd.freq0;
   uint64_t* bits = a.flags + (int64_t)s * nw * a.nwords;
-  constexpr int kG = 16;  // widths loaded together
-  for (int64_t rb = r0 + wave * 64; rb < r0 + kFlagRows && rb < sd.rows; rb += kPeakThreads) {
-    const int64_t r = rb + lane;
-    const bool in = r < sd.rows;
-    const double x = in ? lx[r] : 0.0;
+  // two 64-row steps and up to kG widths loaded together, then tested
+  constexpr int kG = 10, kU = 2;
+  for (int64_t rb = r0 + wave * 64; rb < r0 + kFlagRows && rb < sd.rows; rb += kU * kPeakThreads) {
     for (int w0 = 0; w0 < nw; w0 += kG) {
-      float v[kG];
+      float v[kU][kG];
+      double x[kU];
 #pragma unroll
-      for (int g = 0; g < kG; ++g) v[g] = (in && w0 + g < nw) ? snr[r * nw + w0 + g] : 0.0f;
+      for (int q = 0; q < kU; ++q) {
+        const int64_t r = rb + q * kPeakThreads + lane;
+        const bool in = r < sd.rows && rb + q * kPeakThreads < r0 + kFlagRows;
+        x[q] = in ? lx[r] : 0.0;
 #pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const int w = w0 + g;
-        if (w >= nw) break;  // uniform
-        const PeakFitDev& f = fit[w];
-        const double u = (x - f.xbar) * f.inv_scale;
-        // coefficients past the degree are zero, so the full-degree Horner
-        // form gives the degree-d value exactly
-        double t = f.c[kPeakMaxDegree];
+        for (int g = 0; g < kG; ++g) v[q][g] = (in && w0 + g < nw) ? snr[r * nw + w0 + g] : 0.0f;
+      }
 #pragma unroll
-        for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
-        const bool flag = in && f.ok && (double)v[g] > t;  // false for a NaN S/N
-        const unsigned long long m = __ballot(flag);
-        if (lane == 0) bits[(int64_t)w * a.nwords + (rb >> 6)] = m;
+      for (int q = 0; q < kU; ++q) {
+        const int64_t rq = rb + q * kPeakThreads;  // first row of this step
+        if (rq >= sd.rows || rq >= r0 + kFlagRows) break;  // uniform
+        const bool in = rq + lane < sd.rows;
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+          const int w = w0 + g;
+          if (w >= nw) break;  // uniform
+          const PeakFitDev& f = fit[w];
+          const double u = (x[q] - f.xbar) * f.inv_scale;
+          // coefficients past the degree are zero, so the full-degree Horner
+          // form gives the degree-d value exactly
+          double t = f.c[kPeakMaxDegree];
+#pragma unroll
+          for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
+          const bool flag = in && f.ok && (double)v[q][g] > t;  // false for a NaN S/N
+          const unsigned long long m = __ballot(flag);
+          if (lane == 0) bits[(int64_t)w * a.nwords + (rq >> 6)] = m;
+        }
       }
     }
   }
