@@ -56,7 +56,7 @@ def parse():
                     help="1: also time peak detection (Sec. 5.5) on the headline variant's "
                          "periodograms, reported apart from the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="batch", choices=["batch", "uneven"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "uneven", "single"])
     ap.add_argument("--autotune", type=int, default=0,
                     help="autotune the tiling on --tune-series series first (the default tiling "
                          "is what the tuner picks for the batch workload)")
@@ -296,6 +296,66 @@ def main_uneven(a):
         "variants": out}), flush=True)
 
 
+def main_single(a):
+    """Single series (workloads 1 and 2): launch- and latency-bound searches,
+    timed as eager per-pass launches, as hipGraph replays, and as graph
+    replays of one persistent launch, next to the oracle on the same series."""
+    import torch
+    import paper_2004_03701_amd as ffa
+    import oracle
+    import synth
+    ctx = ffa.ffa_create(0)
+    out = {}
+    for wl, make in (("workload1", synth.workload1), ("workload2", synth.workload2)):
+        x, cfg, _ = make()
+        dev = torch.from_numpy(x.astype(np.float32)).cuda()
+        prm = ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                              cfg.bins_max, cfg.widths)
+        rows = ffa.ffa_plan_rows(prm, dev.numel())
+        snr = torch.empty((rows, len(cfg.widths)), dtype=torch.float32, device="cuda")
+        res = {"samples": int(dev.numel()), "profiles": rows}
+        for name, persistent, graph in (("eager", 0, False), ("graph", 0, True),
+                                        ("persistent_graph", 1, True)):
+            ffa.ffa_set_tiling(ctx, persistent=persistent)
+            for _ in range(max(a.warmup, 1)):
+                ffa.ffa_search_batch(ctx, [dev], [prm], snr=snr, use_graph=graph)
+            torch.cuda.synchronize()
+            reps = 10 * a.steps
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ffa.ffa_search_batch(ctx, [dev], [prm], snr=snr, use_graph=graph)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            res[name] = {"ms_per_search": ms, "profiles_per_s": rows / (ms * 1e-3)}
+            log(f"{wl} {name}: {ms:.3f} ms")
+        ffa.ffa_set_tiling(ctx)
+        if a.cpu_baseline:
+            t0 = time.perf_counter()
+            oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                          cfg.bins_max, cfg.widths)
+            dt = time.perf_counter() - t0
+            res["cpu_oracle"] = {"ms_per_search": 1e3 * dt, "profiles_per_s": rows / dt,
+                                 "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                             os.cpu_count() or 1))}
+        out[wl] = res
+        del dev, snr
+    ffa.ffa_destroy(ctx)
+    best = max(out["workload2"][k]["profiles_per_s"] for k in ("eager", "graph",
+                                                                 "persistent_graph"))
+    r2 = out["workload2"]
+    print(json.dumps({
+        "metric": "trial profiles/sec (FFA+S/N), one series, 1 GPU",
+        "value": best, "unit": "profiles/s", "n_gpus": 1, "steps": 10 * a.steps,
+        "warmup": a.warmup, "ms_per_step": min(r2[k]["ms_per_search"] for k in
+                                               ("eager", "graph", "persistent_graph")),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "workload 2: 9,375,000 samples at 64 us, periods 0.5-10 s, "
+                               "bins 240-259, 9 widths (workload 1: 2^18 samples, periods "
+                               "128-256 samples, bins 128-255, also reported)"},
+        "variants": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -303,6 +363,8 @@ def main():
         sys.exit(2)
     if a.workload == "uneven":
         return main_uneven(a)
+    if a.workload == "single":
+        return main_single(a)
     import torch
     import paper_2004_03701_amd as ffa
     import synth

@@ -139,5 +139,7 @@ def test_null_context_is_rejected_without_device_work():
     assert L.ffa_find_peaks_batch(None, 1, ctypes.byref(ctypes.c_int64(10)), ctypes.byref(prm),
                                   ctypes.byref(ctypes.c_int64(0)), None, 0, ctypes.byref(pk),
                                   None, 0, ctypes.byref(n), None, None) == ffa.FFA_ERR_INVALID_ARG
+    assert L.ffa_search_ranges(None, None, 10, ctypes.byref(prm), 1, None, None, None, None, 0,
+                               None) == ffa.FFA_ERR_INVALID_ARG
     assert L.ffa_destroy(None) == ffa.FFA_OK
     assert L.ffa_create(0, None) == ffa.FFA_ERR_INVALID_ARG
