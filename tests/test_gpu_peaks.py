@@ -167,6 +167,31 @@ def test_peaks_of_searched_periodograms(ctx, pp_args):
     check_against_oracle(got, counts, poly, host, row_offset, prms, nsamps, pp)
 
 
+def test_peaks_full_size_batch(ctx):
+    # the bench's shape: full 2^23-sample workload-3 series in one batch
+    # (here 8, two of them pulsed), default peak parameters; three series
+    # checked against the oracle
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    quiet = [i for i in range(synth.WL3_SERIES) if i not in set(pulsed.tolist())][:6]
+    idx = [int(pulsed[3]), quiet[0], int(pulsed[4])] + quiet[1:6]
+    print(f"peaks: full-size batch {idx}", flush=True)
+    xs = [synth.workload3_series(i, pulsed=pulsed)[0] for i in idx]
+    prms = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                            cfg.bins_max, cfg.widths) for _ in xs]
+    series = [torch.from_numpy(x.astype(np.float32)).cuda() for x in xs]
+    n = synth.WL3_NSAMP
+    snr, row_offset = ffa.ffa_search_batch(ctx, series, prms)
+    pp = ffa.make_peak_params()
+    got, counts, poly = ffa.ffa_find_peaks_batch(ctx, snr, prms, [n] * len(xs), row_offset, pp)
+    host = snr.cpu().numpy()
+    print(f"peaks per series {counts.tolist()}", flush=True)
+    pick = [0, 1, 2]
+    sub = got[np.isin(got["series"], pick)]
+    check_against_oracle(sub, counts[pick], poly[pick], host, [row_offset[i] for i in pick],
+                         [prms[i] for i in pick], [n] * len(pick), pp)
+
+
 def test_peak_capacity_degenerate_and_errors(ctx):
     print("peaks: capacity, NaN periodogram, argument errors", flush=True)
     prm = small_params()
