@@ -155,7 +155,7 @@ struct ffa_ctx {
   std::string pk_key;    // batch the peak-detection tables were uploaded for
   int32_t pk_max_nseg = 0, pk_max_seg = 0, pk_nmid = 0, pk_nbig = 0;
   int num_cus = 256;
-  size_t scratch_budget_cells = size_t(1) << 30;  // floats per scratch buffer
+  size_t scratch_budget_cells = size_t(1) << 32;  // floats per scratch buffer (16 GiB)
 };
 
 namespace {
