@@ -122,6 +122,11 @@ def test_cluster_gap_rule():
     assert pk.cluster(np.arange(6), nu, snr, 0.3) == [(1, 3), (3, 3)]
     assert pk.cluster(np.arange(6), nu, snr, 0.45) == [(3, 6)]
     assert pk.cluster(np.zeros(0, dtype=np.int64), nu, snr, 0.1) == []
+    # a step exactly equal to the gap keeps the cluster together (only a
+    # larger step splits it); the frequencies are exact binary fractions
+    nu2 = np.array([1.0, 0.75, 0.5, 0.125])
+    s2 = np.array([1.0, 3.0, 2.0, 4.0])
+    assert pk.cluster(np.arange(4), nu2, s2, 0.25) == [(1, 3), (3, 1)]
 
 
 def test_small_and_non_finite_segments_give_no_control_point():
@@ -134,6 +139,11 @@ def test_small_and_non_finite_segments_give_no_control_point():
     snr[np.flatnonzero(bad)[3]] = np.nan
     xs, ys, ids = pk.control_points(snr, seg, nu_lo, dnu, prm)
     assert 7 not in ids and 6 in ids and 8 in ids
+    # exactly min_points rows give a control point, one fewer none
+    seg2 = np.array([1] * 16 + [0] * 15)
+    v2 = np.linspace(0.0, 1.0, seg2.size)
+    ids2 = pk.control_points(v2, seg2, 0.1, 0.01, pk.PeakParams(min_points=16))[2]
+    assert list(ids2) == [1]
     big = pk.PeakParams(min_points=10 ** 6)
     assert pk.control_points(snr, seg, nu_lo, dnu, big)[0].size == 0
     # no control points: no threshold, no peaks
