@@ -366,6 +366,33 @@ def test_workload3_full_size_batch_and_low_precision(ctx):
         assert all(a == b for a, b in found)
 
 
+def test_workload3_batch_spanning_two_scratch_groups(ctx):
+    # 72 full-size workload-3 series need two scratch groups (two launches per
+    # group, the benchmark's grouping); series from both groups against the oracle
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    n = 72
+    print(f"two scratch groups: {n} series of 2^23", flush=True)
+    xs = [synth.workload3_series(i, pulsed=pulsed)[0] for i in range(n)]
+    series = [dev(x) for x in xs]
+    prm = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min, cfg.bins_max,
+                           cfg.widths) for _ in xs]
+    ffa.ffa_set_timing(ctx, True)
+    ffa.ffa_read_timing(ctx, reset=True)
+    snr, offs = ffa.ffa_search_batch(ctx, series, prm)
+    torch.cuda.synchronize()
+    tm = ffa.ffa_read_timing(ctx, reset=True)
+    ffa.ffa_set_timing(ctx, False)
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    assert tm["fold_launches"] == 4, tm["fold_launches"]
+    host = snr.cpu().numpy().astype(np.float64)
+    for i in (0, 40, n - 1):
+        ref = oracle.search(xs[i], cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                            cfg.bins_max, cfg.widths)
+        got = host[offs[i]:offs[i] + ref.snr.shape[0]]
+        assert snr_close(got, ref.snr) < SNR_RTOL, i
+
+
 def test_persistent_launch_equals_pass_launches(ctx):
     # same tiles either way: the periodograms are bit-identical
     xs, cfgs = batch_inputs(5)
