@@ -250,7 +250,8 @@ def cpu_baseline(seconds, nsamp):
 
 def main_uneven(a):
     """The uneven batch (256 series of 2^20..2^24 samples, three sampling
-    times, two period ranges): autotuned tiling against the fixed default."""
+    times, two period ranges): tiling autotuned on the first 4 x --tune-series
+    series against the fixed default, both timed on the whole batch."""
     import torch
     import paper_2004_03701_amd as ffa
     import synth
@@ -270,9 +271,12 @@ def main_uneven(a):
     for name in ("default", "autotuned"):
         ffa.ffa_set_tiling(ctx)
         if name == "autotuned":
-            t = ffa.ffa_autotune(ctx, xs, prm)
+            k = min(len(xs), 4 * a.tune_series)  # a representative share of the batch
+            t = ffa.ffa_autotune(ctx, xs[:k], prm[:k])
+            log(f"autotuned on {k} series")
             out["tiling"] = {"waves_per_group": t.waves_per_group,
-                             "levels_per_pass": t.levels_per_pass, "persistent": t.persistent}
+                             "levels_per_pass": t.levels_per_pass, "persistent": t.persistent,
+                             "lds_rows": t.lds_rows}
         for _ in range(a.warmup):
             ffa.ffa_search_batch(ctx, xs, prm, snr=snr)
         torch.cuda.synchronize()

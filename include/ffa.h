@@ -201,7 +201,8 @@ ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out);
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* tiling);
 
 /* Times candidate tilings (8 or 16 waves per workgroup, 3, 4 or 5 levels per
- * pass, per-pass or persistent launches) on a representative batch (same
+ * pass, per-pass or persistent launches, the largest tile that fits or tiles
+ * of at most 40 rows) on a representative batch (same
  * arguments as ffa_search_batch; outputs go to a context-owned buffer) with
  * HIP events on `stream`, keeps the fastest in the context and, if cache_path
  * is not NULL, appends it to that text file keyed by a hash of the batch's

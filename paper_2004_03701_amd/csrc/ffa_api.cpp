@@ -986,6 +986,10 @@ ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset) {
   return FFA_OK;
 }
 
+// Rows of the smaller tile shape the autotuner tries next to the largest
+// that fits (0): enough for the depth-5 subtrees of a 1073-row transform.
+constexpr int32_t kTuneSmallTileRows = 40;
+
 ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                         const int64_t* nsamp, const ffa_search_params* params,
                         const char* cache_path, ffa_tiling* best, void* stream) {
@@ -1060,12 +1064,13 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
   ctx->timing = false;
   for (int waves : {kWavesSmall, kWavesLarge})
     for (int levels : {3, 4, 5})
-      for (int persistent : {0, 1}) {
+      for (int persistent : {0, 1})
+      for (int lds_rows : {0, kTuneSmallTileRows}) {
         Tiling t;
         t.waves = waves;
         t.levels_per_pass = levels;
         t.persistent = persistent;
-        t.lds_rows = 0;
+        t.lds_rows = lds_rows;
         ctx->tiling = t;
         // first call builds the tables and warms the caches
         st = run_batch(ctx, nseries, series, nsamp, params, offs.data(), out, rows, 0, hs);

@@ -446,12 +446,14 @@ def test_autotune_uneven_batch_and_cache(ctx, tmp_path):
     try:
         best = ffa.ffa_autotune(ctx, dev_x, params, cache_path=cache)
         assert best.waves_per_group in (8, 16) and 1 <= best.levels_per_pass <= 5
+        assert best.lds_rows in (0, 40)
         got, _ = ffa.ffa_search_batch(ctx, dev_x, params)
         torch.cuda.synchronize()
         assert snr_close(got.cpu().numpy(), ref.cpu().numpy().astype(np.float64)) < 2e-6
         again = ffa.ffa_autotune(ctx, dev_x, params, cache_path=cache)
-        assert (again.waves_per_group, again.levels_per_pass, again.persistent) == \
-            (best.waves_per_group, best.levels_per_pass, best.persistent)
+        assert (again.waves_per_group, again.levels_per_pass, again.persistent,
+                again.lds_rows) == (best.waves_per_group, best.levels_per_pass,
+                                    best.persistent, best.lds_rows)
         assert len(open(cache).read().strip().splitlines()) == 1
     finally:
         ffa.ffa_set_tiling(ctx)
