@@ -64,6 +64,10 @@ struct DevBuf {
 };
 
 
+// Smallest scratch budget (floats per buffer) a call lowers the context's to
+// when the device cannot allocate the scratch of larger groups.
+constexpr size_t kMinScratchBudgetCells = size_t(1) << 26;
+
 // Key of a plan: every parameter that changes it.
 std::string plan_key(const ffa_search_params& a, int64_t nsamp) {
   std::ostringstream k;
@@ -155,7 +159,8 @@ struct ffa_ctx {
   std::string pk_key;    // batch the peak-detection tables were uploaded for
   int32_t pk_max_nseg = 0, pk_max_seg = 0, pk_nmid = 0, pk_nbig = 0;
   int num_cus = 256;
-  size_t scratch_budget_cells = size_t(1) << 32;  // floats per scratch buffer (16 GiB)
+  size_t scratch_budget_cells = size_t(1) << 32;  // floats per scratch buffer (16 GiB); a
+                                                  // call that cannot allocate it lowers it
 };
 
 namespace {
@@ -528,18 +533,31 @@ ffa_status run_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     if (row_offset[i] < 0 || row_offset[i] + plans[i]->rows > capacity_rows)
       return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
   }
-  const std::string key = job_key(nseries, series, nsamp, params, row_offset, ctx->tiling);
+  std::string key;
   std::shared_ptr<Job> job;
-  auto it = ctx->jobs.find(key);
-  if (it != ctx->jobs.end()) {
-    job = it->second;
-  } else {
-    if (ctx->jobs.size() > 64) ctx->jobs.clear();
-    job = std::make_shared<Job>();
-    st = build_job(ctx, nseries, series, nsamp, params, row_offset, plans, job.get());
-    if (st != FFA_OK) return st;
-    ctx->jobs[key] = job;
+  for (;;) {
+    key = job_key(nseries, series, nsamp, params, row_offset, ctx->tiling);
+    auto it = ctx->jobs.find(key);
+    if (it != ctx->jobs.end()) {
+      job = it->second;
+    } else {
+      if (ctx->jobs.size() > 64) ctx->jobs.clear();
+      job = std::make_shared<Job>();
+      st = build_job(ctx, nseries, series, nsamp, params, row_offset, plans, job.get());
+      if (st != FFA_OK) return st;
+      ctx->jobs[key] = job;
+    }
+    st = reserve_job(ctx, *job);
+    if (st != FFA_ERR_NOMEM || ctx->scratch_budget_cells <= kMinScratchBudgetCells) break;
+    // the device cannot hold the scratch of groups this large: smaller
+    // groups (more launches) with buffers a quarter the size
+    ctx->scratch_budget_cells /= 4;
+    ctx->jobs.clear();
+    ctx->graphs.clear();
+    (void)hipGetLastError();  // the failed allocation must not be reported by a later launch
+    ctx->last_error.clear();
   }
+  if (st != FFA_OK) return st;
   if (!use_graph) return enqueue_job(ctx, *job, snr, stream, ctx->timing);
   std::ostringstream gk;
   gk << key << "|snr=" << (const void*)snr << "|stream=" << (const void*)stream;

@@ -393,6 +393,44 @@ def test_workload3_batch_spanning_two_scratch_groups(ctx):
         assert snr_close(got, ref.snr) < SNR_RTOL, i
 
 
+def test_smaller_scratch_groups_when_memory_is_short():
+    # a fresh context on a device with only 6 GB free: the 20-series batch's
+    # scratch (two buffers of 5 GB) does not fit, the call lowers the scratch
+    # budget until it does (groups of 4 series) and still returns the right
+    # periodogram
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    n = 20
+    xs = [synth.workload3_series(i, pulsed=pulsed)[0] for i in range(n)]
+    series = [dev(x) for x in xs]
+    prm = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min, cfg.bins_max,
+                           cfg.widths) for _ in xs]
+    rows = [ffa.ffa_plan_rows(q, x.size) for q, x in zip(prm, xs)]
+    snr = torch.empty((sum(rows), len(cfg.widths)), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    fill = free - (6 << 30)
+    print(f"short memory: {free / 2**30:.1f} GiB free, holding {fill / 2**30:.1f} GiB", flush=True)
+    filler = torch.empty(max(fill, 0), dtype=torch.uint8, device="cuda")
+    c = ffa.ffa_create(0)
+    try:
+        ffa.ffa_set_timing(c, True)
+        got, offs = ffa.ffa_search_batch(c, series, prm, snr=snr)
+        torch.cuda.synchronize()
+        tm = ffa.ffa_read_timing(c, reset=True)
+        assert ffa.ffa_sync_status(c) == ffa.FFA_OK
+    finally:
+        ffa.ffa_destroy(c)
+        del filler
+        torch.cuda.empty_cache()
+    assert tm["fold_launches"] == 10, tm["fold_launches"]  # 5 groups of 4 series, 2 passes
+    host = got.cpu().numpy().astype(np.float64)
+    for i in (0, n - 1):
+        ref = oracle.search(xs[i], cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                            cfg.bins_max, cfg.widths)
+        assert snr_close(host[offs[i]:offs[i] + ref.snr.shape[0]], ref.snr) < SNR_RTOL, i
+
+
 def test_persistent_launch_equals_pass_launches(ctx):
     # same tiles either way: the periodograms are bit-identical
     xs, cfgs = batch_inputs(5)
