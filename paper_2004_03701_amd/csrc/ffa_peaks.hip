@@ -19,7 +19,8 @@
 //                wave, and the normal equations solved in FP64;
 //   k_peak_flag / k_peak_cluster
 //                every row's thresholds, the rows above them as one bit per
-//                (row, width) from wave ballots; then one wave per (series,
+//                (row, width) from wave ballots (the S/N read as whole rows,
+//                transposed through LDS); then one wave per (series,
 //                width) lists the set rows in row (= frequency) order and
 //                one lane walks them forming the clusters.
 #include <hip/hip_runtime.h>
@@ -459,13 +460,17 @@ __device__ __forceinline__ void emit_peak(const PeakArgs& a, int s, int w, int64
 
 // Selection: every row's thresholds and the rows above them, as one bit per
 // (row, width). A workgroup takes kFlagRows consecutive rows of one series;
-// a wave reads 64 whole rows (every width, coalesced) per step and one
+// a wave takes 64 whole rows per step: it reads their 64 x num_widths S/N
+// values as consecutive words (each load instruction covers 64 consecutive
+// words), parks them in its own LDS area, reads back row = lane, and one
 // ballot per width gives the 64 bits of that width.
 constexpr int kFlagRows = 4096;
+constexpr int kFlagSteps = 2;  // 64-row steps a wave loads together
 
 __global__ __launch_bounds__(kPeakThreads) void k_peak_flag(PeakArgs a) {
   constexpr int kMaxW = 32;
   __shared__ PeakFitDev fit[kMaxW];
+  extern __shared__ float stage[];  // per wave: kFlagSteps x 64 x num_widths
   const int nw = a.num_widths;
   const int chunks = (int)((a.nwords * 64 + kFlagRows - 1) / kFlagRows);
   const int s = blockIdx.x / chunks, c = blockIdx.x - s * chunks;
@@ -478,40 +483,54 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_flag(PeakArgs a) {
   const float* snr = a.snr + sd.snr_row0 * nw;
   const double* lx = a.lognu + sd.freq0;
   uint64_t* bits = a.flags + (int64_t)s * nw * a.nwords;
-  // two 64-row steps and up to kG widths loaded together, then tested
-  constexpr int kG = 10, kU = 2;
-  for (int64_t rb = r0 + wave * 64; rb < r0 + kFlagRows && rb < sd.rows; rb += kU * kPeakThreads) {
-    for (int w0 = 0; w0 < nw; w0 += kG) {
-      float v[kU][kG];
-      double x[kU];
+  float* my = stage + wave * kFlagSteps * 64 * nw;
+  const int64_t rend = min(sd.rows, r0 + kFlagRows);
+  for (int64_t rb = r0 + wave * 64; rb < rend; rb += kFlagSteps * kPeakThreads) {
+    double x[kFlagSteps];
+    // every load of both steps in flight before the first LDS store: up to
+    // kLoadW words per lane and step at a time
+    constexpr int kLoadW = 16;
+    for (int i0 = 0; i0 < nw; i0 += kLoadW) {
+      float buf[kFlagSteps][kLoadW];
 #pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        const int64_t r = rb + q * kPeakThreads + lane;
-        const bool in = r < sd.rows && rb + q * kPeakThreads < r0 + kFlagRows;
-        x[q] = in ? lx[r] : 0.0;
+      for (int q = 0; q < kFlagSteps; ++q) {
+        const int64_t rq = rb + q * kPeakThreads;  // first row of this step
+        const int words = rq < rend ? (int)min((int64_t)64, rend - rq) * nw : 0;
+        const float* src = snr + rq * nw;
 #pragma unroll
-        for (int g = 0; g < kG; ++g) v[q][g] = (in && w0 + g < nw) ? snr[r * nw + w0 + g] : 0.0f;
+        for (int i = 0; i < kLoadW; ++i) {
+          const int t = (i0 + i) * 64 + lane;
+          buf[q][i] = (i0 + i < nw && t < words) ? src[t] : 0.0f;
+        }
       }
 #pragma unroll
-      for (int q = 0; q < kU; ++q) {
-        const int64_t rq = rb + q * kPeakThreads;  // first row of this step
-        if (rq >= sd.rows || rq >= r0 + kFlagRows) break;  // uniform
-        const bool in = rq + lane < sd.rows;
+      for (int q = 0; q < kFlagSteps; ++q)
 #pragma unroll
-        for (int g = 0; g < kG; ++g) {
-          const int w = w0 + g;
-          if (w >= nw) break;  // uniform
-          const PeakFitDev& f = fit[w];
-          const double u = (x[q] - f.xbar) * f.inv_scale;
-          // coefficients past the degree are zero, so the full-degree Horner
-          // form gives the degree-d value exactly
-          double t = f.c[kPeakMaxDegree];
+        for (int i = 0; i < kLoadW; ++i)
+          if (i0 + i < nw) my[q * 64 * nw + (i0 + i) * 64 + lane] = buf[q][i];
+    }
 #pragma unroll
-          for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
-          const bool flag = in && f.ok && (double)v[q][g] > t;  // false for a NaN S/N
-          const unsigned long long m = __ballot(flag);
-          if (lane == 0) bits[(int64_t)w * a.nwords + (rq >> 6)] = m;
-        }
+    for (int q = 0; q < kFlagSteps; ++q) {
+      const int64_t rq = rb + q * kPeakThreads;
+      x[q] = rq + lane < rend ? lx[rq + lane] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kFlagSteps; ++q) {
+      const int64_t rq = rb + q * kPeakThreads;
+      if (rq >= rend) break;  // uniform
+      const bool in = rq + lane < rend;
+      const float* row = my + q * 64 * nw + lane * nw;
+      for (int w = 0; w < nw; ++w) {
+        const PeakFitDev& f = fit[w];
+        const double u = (x[q] - f.xbar) * f.inv_scale;
+        // coefficients past the degree are zero, so the full-degree Horner
+        // form gives the degree-d value exactly
+        double t = f.c[kPeakMaxDegree];
+#pragma unroll
+        for (int j = kPeakMaxDegree - 1; j >= 0; --j) t = t * u + f.c[j];
+        const bool flag = in && f.ok && (double)row[w] > t;  // false for a NaN S/N
+        const unsigned long long m = __ballot(flag);
+        if (lane == 0) bits[(int64_t)w * a.nwords + (rq >> 6)] = m;
       }
     }
   }
@@ -675,7 +694,16 @@ hipError_t launch_peak_fit(const PeakArgs& a, hipStream_t stream) {
 hipError_t launch_peak_scan(const PeakArgs& a, hipStream_t stream) {
   if (a.nseries <= 0 || a.nwords <= 0) return hipSuccess;
   const int chunks = (int)((a.nwords * 64 + kFlagRows - 1) / kFlagRows);
-  hipLaunchKernelGGL(k_peak_flag, dim3(a.nseries * chunks), dim3(kPeakThreads), 0, stream, a);
+  static bool attr = false;  // up to 32 widths: 64 KiB of staging
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_peak_flag),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_peak_flag, dim3(a.nseries * chunks), dim3(kPeakThreads),
+                     (kPeakThreads / 64) * kFlagSteps * 64 * a.num_widths * sizeof(float), stream,
+                     a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_peak_cluster, dim3(a.nseries * a.num_widths), dim3(64), 0, stream, a);
