@@ -212,8 +212,20 @@ __global__ __launch_bounds__(64 * kSegWidths) void k_peak_ctrl_seg(PeakArgs a) {
     if (lane == 0) *out = NAN;
     return;
   }
+  // n * nw <= 16 * blockDim words: every load of a thread in flight before
+  // its first LDS store
   const float* src = a.snr + (sd.snr_row0 + rb) * nw;
-  for (int q = threadIdx.x; q < n * nw; q += blockDim.x) seg[q] = src[q];
+  float buf[kWaveSortMax / 64];
+#pragma unroll
+  for (int k = 0; k < kWaveSortMax / 64; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    buf[k] = q < n * nw ? src[q] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kWaveSortMax / 64; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    if (q < n * nw) seg[q] = buf[k];
+  }
   __syncthreads();
   float v[16];
   bool bad = false;
