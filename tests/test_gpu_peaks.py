@@ -125,6 +125,25 @@ def test_peaks_of_constructed_periodograms(ctx):
     assert np.max(np.abs(np.polynomial.polynomial.polyval(x, poly[1, 0]) - want)) < 1e-4
 
 
+@pytest.mark.parametrize("nw", [13, 32])
+def test_peaks_with_many_widths(ctx, nw):
+    # more than 12 widths: one wave per (segment, width) instead of one
+    # workgroup per segment; 32 widths: two load batches in the selection
+    prm = ffa.make_params(1.0, 128.0, 256.0, 128, 255, tuple(range(1, nw + 1)), normalise=False)
+    n = 1 << 18
+    per = oracle_periods(prm, n)
+    g = np.random.Generator(np.random.Philox(9300 + nw))
+    host = (3.0 + 0.5 * g.standard_normal((per.size, nw))).astype(np.float32)
+    host[4000:4003, nw - 1] = [11.0, 14.0, 12.0]
+    host[100000, 5] = 10.0
+    print(f"peaks: {nw} widths", flush=True)
+    snr = torch.from_numpy(host).cuda()
+    pp = ffa.make_peak_params()
+    got, counts, poly = ffa.ffa_find_peaks_batch(ctx, snr, [prm], [n], [0], pp)
+    check_against_oracle(got, counts, poly, host, [0], [prm], [n], pp)
+    assert {(int(q["width_index"]), int(q["row"])) for q in got} >= {(nw - 1, 4001), (5, 100000)}
+
+
 @pytest.mark.parametrize("dz_seg", [6.0, 10.0, 30.0])
 def test_peaks_with_larger_segments(ctx, dz_seg):
     # segments of 1025 .. 2048 rows take the two-wave sort, larger ones the
