@@ -1826,14 +1826,10 @@ template <int DT, int DO>
 hipError_t launch_downsample_t(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
                                const float* norm, void* out, int64_t nblocks, size_t lds,
                                hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_downsample<DT, DO>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kLdsBytes - 4096);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool done[kMaxDevices] = {};
+  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_downsample<DT, DO>),
+                                    kLdsBytes - 4096, done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_downsample<DT, DO>), dim3((unsigned)nblocks), dim3(kDsThreads), lds,
                      stream, series_dev, nseries, oct, norm, out);
   return hipGetLastError();
@@ -1866,14 +1862,10 @@ int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {
 
 template <int WV, int JS, int DT>
 hipError_t launch_persist_t(const PassArgs& args, int grid, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_persist<WV, JS, DT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       wg_lds_bytes(WV));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool done[kMaxDevices] = {};
+  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_ffa_persist<WV, JS, DT>),
+                                    wg_lds_bytes(WV), done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_ffa_persist<WV, JS, DT>), dim3(grid), dim3(WV * 64), wg_lds_bytes(WV),
                      stream, args);
   return hipGetLastError();
@@ -1881,14 +1873,10 @@ hipError_t launch_persist_t(const PassArgs& args, int grid, hipStream_t stream) 
 
 template <int WV, int JS, int DT>
 hipError_t launch_pass_t(const PassArgs& args, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ffa_pass<WV, JS, DT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       wg_lds_bytes(WV));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool done[kMaxDevices] = {};
+  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_ffa_pass<WV, JS, DT>),
+                                    wg_lds_bytes(WV), done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_ffa_pass<WV, JS, DT>), dim3(args.ntiles), dim3(WV * 64), wg_lds_bytes(WV),
                      stream, args);
   return hipGetLastError();

@@ -62,6 +62,19 @@ hipError_t launch_persist(const PassArgs& args, int ncounters, int grid, hipStre
 // LDS bytes a pass launch uses.
 int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p);
 
+// Raises a kernel's dynamic-LDS limit to `bytes` on the current device, once
+// per device (done[] holds one flag per device, kMaxDevices of them).
+constexpr int kMaxDevices = 64;
+inline hipError_t set_lds_limit_once(const void* kernel, int bytes, bool* done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < kMaxDevices && done[dev]) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess && dev >= 0 && dev < kMaxDevices) done[dev] = true;
+  return e;
+}
+
 // Sets a flag word to zero with a kernel (graph-capture friendly).
 hipError_t launch_clear_flag(int32_t* flag, hipStream_t stream);
 

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "ffa_kernels.hpp"
 #include "ffa_peaks.hpp"
 
 namespace ffa {
@@ -706,17 +707,13 @@ hipError_t launch_peak_fit(const PeakArgs& a, hipStream_t stream) {
 hipError_t launch_peak_scan(const PeakArgs& a, hipStream_t stream) {
   if (a.nseries <= 0 || a.nwords <= 0) return hipSuccess;
   const int chunks = (int)((a.nwords * 64 + kFlagRows - 1) / kFlagRows);
-  static bool attr = false;  // up to 32 widths: 64 KiB of staging
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_peak_flag),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static bool done[kMaxDevices] = {};  // up to 32 widths: 64 KiB of staging
+  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_peak_flag), 96 * 1024, done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_peak_flag, dim3(a.nseries * chunks), dim3(kPeakThreads),
                      (kPeakThreads / 64) * kFlagSteps * 64 * a.num_widths * sizeof(float), stream,
                      a);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_peak_cluster, dim3(a.nseries * a.num_widths), dim3(64), 0, stream, a);
   return hipGetLastError();
