@@ -466,6 +466,44 @@ def test_search_tilings_agree(ctx, lds_rows, levels, persistent, waves):
     assert snr_close(got, ref.astype(np.float64)) < 2e-6
 
 
+def test_workload5_full_uneven_batch(ctx):
+    # the uneven batch at its full size, as the benchmark runs it: 256 series
+    # of 2^20..2^24 samples, three sampling times and two period ranges in one
+    # batched call with the default tiling (transforms of up to ~21,000 rows,
+    # three passes); the shortest and longest series and one of every
+    # (sampling time, period range) pair against the oracle
+    xs, cfgs, keys = [], [], []
+    for i in range(256):
+        x, cfg, _ = synth.workload5_series(i)
+        xs.append(x)
+        cfgs.append(cfg)
+        keys.append((cfg.tsamp, cfg.period_min))
+        if (i + 1) % 64 == 0:
+            print(f"uneven batch: generated {i + 1}/256 series", flush=True)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(c.tsamp, c.period_min, c.period_max, c.bins_min, c.bins_max,
+                              c.widths) for c in cfgs]
+    ffa.ffa_set_tiling(ctx)
+    snr, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    host = snr.cpu().numpy()
+    del dev_x, snr
+    sizes = [x.size for x in xs]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    for k in sorted(set(keys)):
+        pick.add(keys.index(k))
+    assert len(pick) >= 6
+    for i in sorted(pick):
+        c = cfgs[i]
+        print(f"uneven batch: series {i}, {xs[i].size} samples, tsamp {c.tsamp}, "
+              f"periods {c.period_min}-{c.period_max} s", flush=True)
+        ref = oracle.search(xs[i], c.tsamp, c.period_min, c.period_max, c.bins_min, c.bins_max,
+                            c.widths)
+        got = host[offs[i]:offs[i] + ref.snr.shape[0]]
+        assert snr_close(got, ref.snr) < SNR_RTOL, i
+
+
 def test_autotune_uneven_batch_and_cache(ctx, tmp_path):
     # uneven lengths, sampling times and period ranges (the uneven-batch
     # workload, scaled down); the tuned tiling gives the same periodogram to
