@@ -15,6 +15,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/ffa.h"
 #include "ffa_kernels.hpp"
 
@@ -40,6 +42,8 @@ __device__ __forceinline__ float load_sample(const void* base, int dtype, int64_
 // each load in turn).
 template <class T>
 using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+using gptr_w = __attribute__((address_space(1))) T*;
 
 template <int DT>
 __device__ __forceinline__ float load_g(const void* base, int64_t i) {
@@ -799,16 +803,16 @@ __device__ __forceinline__ void reg_phase(const void* in, int64_t base, int n, i
     for (int r = 0; r < kRegRows; ++r)
 #pragma unroll
       for (int e = 0; e < kChunk; ++e)
-        // 16-bit types: unconditional loads (rows past the node re-read its
-        // last row), so that the conversions are not sunk between them; the
+        // unconditional loads, all in flight together with no branch between
+        // them: rows past the node re-read its last row (the merges of an
+        // nb-row node and the stores below never use rows nb and up); the
         // row start is uniform and the lane's column a 32-bit offset
-        raw[r][e] = DT == FFA_F32 ? (r < nb ? load_row_bits<DT>(in, rb + (int64_t)r * p, col[e]) : 0u)
-                                  : load_row_bits<DT>(in, rb + (int64_t)(r < nb ? r : nb - 1) * p, col[e]);
+        raw[r][e] = load_row_bits<DT>(in, rb + (int64_t)(r < nb ? r : nb - 1) * p, col[e]);
     float v[kRegRows][kChunk];
 #pragma unroll
     for (int r = 0; r < kRegRows; ++r)
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e) v[r][e] = r < nb ? bits_value<DT>(raw[r][e]) : 0.0f;
+      for (int e = 0; e < kChunk; ++e) v[r][e] = bits_value<DT>(raw[r][e]);
     switch (nb) {
       case 2: RegFFA<0, 2>::run(v); break;
       case 3: RegFFA<0, 3>::run(v); break;
@@ -990,33 +994,86 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
   const int width = p + kHalo;
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
   constexpr int KC = 5;
+  // column of copy position c = lane + 64 k (c - p past the row end; shorter
+  // rows than half the copy take a remainder, one uniform branch)
+  uint32_t col[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    col[k] = (uint32_t)(c < p ? c : c - p);
+  }
+  if (2 * p < 64 * KC) {
+#pragma unroll
+    for (int k = 0; k < KC; ++k) col[k] %= (uint32_t)p;
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) col[k] *= 4u;  // byte offsets: a scalar row start plus a vector offset
+  // unconditional loads, with no branch between them: every address is in
+  // the source rows (a row past the wave's count reads the row at offset 0,
+  // the source's first row, and a column past the copy wraps); only the LDS
+  // stores below are conditional
   float v[kStageMax][KC];
 #pragma unroll
   for (int r = 0; r < kStageMax; ++r) {
     const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
                       ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
+    gptr<unsigned char> rp = (gptr<unsigned char>)((gptr<float>)base + g);
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int c = lane + 64 * k;
-      int col = c < p ? c : c - p;
-      if (col >= p) col %= p;
-      v[r][k] = (r < nrw && c < width) ? __builtin_nontemporal_load(&((gptr<float>)base)[g + col]) : 0.0f;
-    }
+    for (int k = 0; k < KC; ++k) v[r][k] = __builtin_nontemporal_load((gptr<float>)(rp + col[k]));
   }
   work();
-#pragma unroll
-  for (int r = 0; r < kStageMax; ++r)
+  auto put = [&](auto all) {
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      const int c = lane + 64 * k;
-      if (r < nrw && c < width) rows[(wave + WV * r) * stride + c] = v[r][k];
+      if (lane + 64 * k < width) {
+#pragma unroll
+        for (int r = 0; r < kStageMax; ++r)
+          if (decltype(all)::value || r < nrw) rows[(wave + WV * r) * stride + lane + 64 * k] = v[r][k];
+      }
     }
+  };
+  if (nrw == kStageMax)
+    put(std::true_type{});
+  else
+    put(std::false_type{});
 }
 
 // Writes rows [0, count) of LDS to global rows dst + q * p, coalesced. The
 // stores are non-temporal: these rows (scratch between passes, or output
 // rows) are read once, by a later launch, and need not displace the
 // downsampled series that the transforms of a pseudo-octave share in L2.
+// The rows of a wave (row wave + WV r for r < nrw, every r when kAll) with
+// one column group per lane: lane l takes columns l + 64 k, those past the
+// row end repeating its last column (such lanes read and store the same
+// value at the same place, so no lane condition is needed).
+template <int WV, bool kAll>
+__device__ __forceinline__ void store_rows_g1(const float* rows, int nrw, int p, int stride, float* dst,
+                                              int wave, int lane) {
+  constexpr int KC = 5;
+  uint32_t cc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    cc[k] = (uint32_t)(c < p ? c : p - 1);
+  }
+  float v[kStageMax][KC];
+#pragma unroll
+  for (int r = 0; r < kStageMax; ++r)
+    if (kAll || r < nrw) {
+      const float* rw = rows + (wave + WV * r) * stride;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) v[r][k] = rw[cc[k]];
+    }
+#pragma unroll
+  for (int r = 0; r < kStageMax; ++r)
+    if (kAll || r < nrw) {
+      // a scalar row start plus a vector byte offset
+      gptr_w<unsigned char> rp = (gptr_w<unsigned char>)((gptr_w<float>)dst + (int64_t)(wave + WV * r) * p);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) __builtin_nontemporal_store(v[r][k], (gptr_w<float>)(rp + 4u * cc[k]));
+    }
+}
+
 template <int WV, int JS>
 __device__ __forceinline__ void store_rows(const float* rows, int count, int p, int stride,
                                            float* dst) {
@@ -1024,22 +1081,10 @@ __device__ __forceinline__ void store_rows(const float* rows, int count, int p, 
   const int lane = threadIdx.x & 63;
   const int nrw = count > wave ? (count - wave + WV - 1) / WV : 0;
   if (JS == 1) {
-    constexpr int KC = 5;
-    float v[kStageMax][KC];
-#pragma unroll
-    for (int r = 0; r < kStageMax; ++r)
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const int c = lane + 64 * k;
-        v[r][k] = (r < nrw && c < p) ? rows[(wave + WV * r) * stride + c] : 0.0f;
-      }
-#pragma unroll
-    for (int r = 0; r < kStageMax; ++r)
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const int c = lane + 64 * k;
-        if (r < nrw && c < p) __builtin_nontemporal_store(v[r][k], &dst[(int64_t)(wave + WV * r) * p + c]);
-      }
+    if (nrw == kStageMax)
+      store_rows_g1<WV, true>(rows, nrw, p, stride, dst, wave, lane);
+    else if (nrw > 0)
+      store_rows_g1<WV, false>(rows, nrw, p, stride, dst, wave, lane);
     return;
   }
   for (int rb = 0; rb < nrw; rb += 4) {
