@@ -96,6 +96,7 @@ struct Job {
   int32_t num_widths = 0;
   int32_t wmax = 0;
   int32_t max_p = 0;
+  int32_t min_p = 0;
   int32_t widths[kMaxWidths] = {0};
   bool any_normalise = false;
   int32_t ds_lds_floats = 0;
@@ -275,6 +276,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
         scales.push_back((float)(1.0 / sqrt((double)t.m * (double)a.widths[q] * var)));
       gcells += (int64_t)t.m * t.p;
       job->max_p = std::max(job->max_p, t.p);
+      job->min_p = job->min_p > 0 ? std::min(job->min_p, t.p) : t.p;
       xf.push_back(x);
     }
     ds_off += pl.ds_total;
@@ -463,6 +465,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   pa.wmax = job.wmax;
   pa.max_p = job.max_p;
   pa.width_set = width_set_of(job.widths, job.num_widths);
+  pa.pairs_only = pairs_only_launch(job.min_p, job.max_p, pa.width_set) ? 1 : 0;
   set_schedules(ctx, &pa);
   pa.ticket = ctx->ticket.as<int32_t>();
   pa.counters = ctx->counters.as<int32_t>();

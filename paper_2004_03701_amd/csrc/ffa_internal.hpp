@@ -127,6 +127,7 @@ struct PassArgs {
   int32_t wmax;
   int32_t max_p;           // largest p of the launch
   int32_t width_set;       // 0: general widths; else a compiled width grid (WidthSet)
+  int32_t pairs_only;      // 1: every tile takes the pair-merge forms (pairs_only_launch)
   // Merge schedules of full subtrees of n rows (2 <= n <= kMaxFullRows):
   // entry full_off[n] + lev * n + q gives, for row q at relative depth lev,
   // the head row (low 16 bits) and tail row (high 16 bits; 0xffff: the row
@@ -161,5 +162,16 @@ enum WidthSet : int32_t {
   kWidthsPaper9 = 1,   // 1,2,3,4,6,9,13,19,28: w0 = 1, w_{k+1} = max(floor(1.5 w_k), w_k + 1)
   kWidthsDuty9 = 2,    // 1,2,3,5,8,12,19,30,48: duty cycles 0.5 % .. 20 % of 240 bins
 };
+
+// Launches in which every tile takes the pair-merge forms (one column group
+// per lane, register levels in full tiles) and the register-window S/N of a
+// compiled width grid: rows of 160 .. max bins with one column group per lane
+// (the S/N window of 32 starts plus the widest boxcar then fits in a row and
+// its copied bins, and the partial maxima fit in the row area of any tile of
+// two or more rows). Such launches run a kernel compiled for those forms only.
+inline __host__ __device__ bool pairs_only_launch(int min_p, int max_p, int width_set) {
+  return width_set != kWidthsGeneral && min_p >= 160 && col_iters(max_p) == 1 &&
+         merge_groups(max_p) + kRegLevels <= 64;
+}
 
 }  // namespace ffa

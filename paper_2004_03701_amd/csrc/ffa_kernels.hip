@@ -1612,7 +1612,9 @@ __device__ __forceinline__ void snr_general(const PassArgs& a, const float* rows
   }
 }
 
-template <int WV, int JS, int DT>
+// PO = 1: a launch whose tiles all take the pair-merge forms and the
+// register-window S/N (pairs_only_launch), compiled without the other forms.
+template <int WV, int JS, int DT, int PO>
 __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, const XformDesc& x,
                                          unsigned char* smem) {
   const int p = x.p, stride = lds_stride(p), J = col_iters(p);
@@ -1642,7 +1644,19 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   int nrows, s_base;
   const int q_lane = wave + WV * lane;  // the wave's row held by this lane
 
-  if ((t.flags & kTileFull) && JS == 1 && merge_groups(p) + kRegLevels <= 64) {
+  if (PO == 1) {
+    static_assert(PO == 0 || JS == 1, "the pair forms need one column group per lane");
+    if (t.flags & kTileFull) {
+      full_tile_pairs<WV, DT>(a, x.in_off + (int64_t)r0 * p, n, p, stride, rows, R);
+      nrows = n;
+      s_base = 0;
+    } else {
+      range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, th,
+                           reinterpret_cast<int*>(snrbuf));
+      nrows = t.s1 - t.s0;
+      s_base = t.s0;
+    }
+  } else if ((t.flags & kTileFull) && JS == 1 && merge_groups(p) + kRegLevels <= 64) {
     full_tile_pairs<WV, DT>(a, x.in_off + (int64_t)r0 * p, n, p, stride, rows, R);
     nrows = n;
     s_base = 0;
@@ -1749,6 +1763,13 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   const float* scale = a.scales + x.scale_off;
   float* out = a.snr + (x.out_row0 + s_base) * a.num_widths;
   const int region = (R + 2) * stride;  // rows, zero row and junk row
+  if (PO == 1) {
+    if (a.width_set == kWidthsPaper9)
+      snr_seg<WV, GridPaper9>(rows, stride, p, nvalid, region, scale, out);
+    else
+      snr_seg<WV, GridDuty9>(rows, stride, p, nvalid, region, scale, out);
+    return;
+  }
   if (a.width_set == kWidthsPaper9) {
     if (snr_seg_fits<GridPaper9>(p, nvalid, region))
       snr_seg<WV, GridPaper9>(rows, stride, p, nvalid, region, scale, out);
@@ -1776,13 +1797,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 
 // One instantiation per (column groups per lane, input storage type): JS = 1
 // needs every tile's p <= 316 (one group per lane); JS = 0 serves any p.
-template <int WV, int JS, int DT>
+template <int WV, int JS, int DT, int PO>
 // Four waves per SIMD: two 8-wave workgroups (or one of 16) per CU, 128 VGPRs.
 __global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_ffa_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc t = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const XformDesc x = a.xf[t.xf];
-  ffa_tile<WV, JS, DT>(a, t, x, smem);
+  ffa_tile<WV, JS, DT, PO>(a, t, x, smem);
 }
 
 // Persistent form: one workgroup per CU takes tiles in ticket order. A tile of
@@ -1825,7 +1846,7 @@ __global__ __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
       __syncthreads();
     }
     const XformDesc x = a.xf[t.xf];
-    ffa_tile<WV, JS, DT>(a, t, x, smem);
+    ffa_tile<WV, JS, DT, 0>(a, t, x, smem);
     // every wave publishes its own global stores before the tile counts
     // itself done
     if (t.done >= 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1916,14 +1937,14 @@ hipError_t launch_persist_t(const PassArgs& args, int grid, hipStream_t stream) 
   return hipGetLastError();
 }
 
-template <int WV, int JS, int DT>
+template <int WV, int JS, int DT, int PO>
 hipError_t launch_pass_t(const PassArgs& args, hipStream_t stream) {
   static bool done[kMaxDevices] = {};
-  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_ffa_pass<WV, JS, DT>),
+  hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_ffa_pass<WV, JS, DT, PO>),
                                     wg_lds_bytes(WV), done);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_ffa_pass<WV, JS, DT>), dim3(args.ntiles), dim3(WV * 64), wg_lds_bytes(WV),
-                     stream, args);
+  hipLaunchKernelGGL((k_ffa_pass<WV, JS, DT, PO>), dim3(args.ntiles), dim3(WV * 64),
+                     wg_lds_bytes(WV), stream, args);
   return hipGetLastError();
 }
 
@@ -1933,8 +1954,10 @@ template <bool kPersist>
 hipError_t dispatch(const PassArgs& args, int grid, hipStream_t stream) {
   const bool j1 = col_iters(args.max_p) == 1;
   const bool big = args.waves == kWavesLarge;
-#define FFA_LAUNCH(WV, JS, DT) \
-  (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream) : launch_pass_t<WV, JS, DT>(args, stream))
+#define FFA_LAUNCH(WV, JS, DT)                                                        \
+  (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream)                        \
+   : (JS == 1 && args.pairs_only) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 1 : 0)>(args, stream) \
+                                  : launch_pass_t<WV, JS, DT, 0>(args, stream))
 // the folded series are FP32 (the downsampler writes FP32 whatever the
 // input's storage type)
 #define FFA_BY_DT(WV, JS) \
