@@ -465,7 +465,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   pa.wmax = job.wmax;
   pa.max_p = job.max_p;
   pa.width_set = width_set_of(job.widths, job.num_widths);
-  pa.pairs_only = pairs_only_launch(job.min_p, job.max_p, pa.width_set) ? 1 : 0;
+  const bool pairs = pairs_only_launch(job.min_p, job.max_p, pa.width_set);
   set_schedules(ctx, &pa);
   pa.ticket = ctx->ticket.as<int32_t>();
   pa.counters = ctx->counters.as<int32_t>();
@@ -483,9 +483,12 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
               "persistent fold kernel");
       continue;
     }
-    for (const Launch& l : g.passes) {
+    for (size_t k = 0; k < g.passes.size(); ++k) {
+      const Launch& l = g.passes[k];
       pa.tiles = tiles + l.tile_off;
       pa.ntiles = l.ntiles;
+      // a first pass holds full tiles only, a later pass range tiles only
+      pa.pairs_only = pairs ? (k == 0 ? 2 : 3) : 0;
       TimedScope ts(ctx, 2, stream, timed);
       HIP_TRY(ctx, launch_pass(pa, stream), "fold pass kernel");
     }

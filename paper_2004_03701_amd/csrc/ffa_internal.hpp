@@ -127,7 +127,8 @@ struct PassArgs {
   int32_t wmax;
   int32_t max_p;           // largest p of the launch
   int32_t width_set;       // 0: general widths; else a compiled width grid (WidthSet)
-  int32_t pairs_only;      // 1: every tile takes the pair-merge forms (pairs_only_launch)
+  int32_t pairs_only;      // every tile takes the pair-merge forms (pairs_only_launch)
+                           // and is full (2) or a range tile (3); 0: any tile
   // Merge schedules of full subtrees of n rows (2 <= n <= kMaxFullRows):
   // entry full_off[n] + lev * n + q gives, for row q at relative depth lev,
   // the head row (low 16 bits) and tail row (high 16 bits; 0xffff: the row

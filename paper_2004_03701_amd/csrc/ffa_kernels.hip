@@ -1612,8 +1612,9 @@ __device__ __forceinline__ void snr_general(const PassArgs& a, const float* rows
   }
 }
 
-// PO = 1: a launch whose tiles all take the pair-merge forms and the
-// register-window S/N (pairs_only_launch), compiled without the other forms.
+// PO = 2 and 3: a launch whose tiles all take the pair-merge forms and the
+// register-window S/N (pairs_only_launch), full tiles only (a first pass) or
+// range tiles only (a later pass), compiled without the other forms.
 template <int WV, int JS, int DT, int PO>
 __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, const XformDesc& x,
                                          unsigned char* smem) {
@@ -1644,9 +1645,9 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   int nrows, s_base;
   const int q_lane = wave + WV * lane;  // the wave's row held by this lane
 
-  if (PO == 1) {
+  if (PO != 0) {
     static_assert(PO == 0 || JS == 1, "the pair forms need one column group per lane");
-    if (t.flags & kTileFull) {
+    if (PO == 2) {
       full_tile_pairs<WV, DT>(a, x.in_off + (int64_t)r0 * p, n, p, stride, rows, R);
       nrows = n;
       s_base = 0;
@@ -1763,7 +1764,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
   const float* scale = a.scales + x.scale_off;
   float* out = a.snr + (x.out_row0 + s_base) * a.num_widths;
   const int region = (R + 2) * stride;  // rows, zero row and junk row
-  if (PO == 1) {
+  if (PO != 0) {
     if (a.width_set == kWidthsPaper9)
       snr_seg<WV, GridPaper9>(rows, stride, p, nvalid, region, scale, out);
     else
@@ -1956,8 +1957,9 @@ hipError_t dispatch(const PassArgs& args, int grid, hipStream_t stream) {
   const bool big = args.waves == kWavesLarge;
 #define FFA_LAUNCH(WV, JS, DT)                                                        \
   (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream)                        \
-   : (JS == 1 && args.pairs_only) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 1 : 0)>(args, stream) \
-                                  : launch_pass_t<WV, JS, DT, 0>(args, stream))
+   : (JS == 1 && args.pairs_only == 2) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 2 : 0)>(args, stream) \
+   : (JS == 1 && args.pairs_only == 3) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 3 : 0)>(args, stream) \
+                                       : launch_pass_t<WV, JS, DT, 0>(args, stream))
 // the folded series are FP32 (the downsampler writes FP32 whatever the
 // input's storage type)
 #define FFA_BY_DT(WV, JS) \
