@@ -995,11 +995,13 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
   const int lo = (int)(src & 0xffffffff), hi = (int)(src >> 32);
   constexpr int KC = 5;
   // column of copy position c = lane + 64 k (c - p past the row end; shorter
-  // rows than half the copy take a remainder, one uniform branch)
+  // rows than half the copy take a remainder, one uniform branch); lanes past
+  // the copy repeat its last position, so they read a line the load reads
+  // anyway (their values are not stored)
   uint32_t col[KC];
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
-    const int c = lane + 64 * k;
+    const int c = min(lane + 64 * k, width - 1);
     col[k] = (uint32_t)(c < p ? c : c - p);
   }
   if (2 * p < 64 * KC) {
@@ -1008,18 +1010,19 @@ __device__ __forceinline__ void load_rows_overlap(float* rows, int count, int p,
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k) col[k] *= 4u;  // byte offsets: a scalar row start plus a vector offset
-  // unconditional loads, with no branch between them: every address is in
-  // the source rows (a row past the wave's count reads the row at offset 0,
-  // the source's first row, and a column past the copy wraps); only the LDS
-  // stores below are conditional
+  // loads without lane conditions (every address is in the row), the rows
+  // past the wave's count skipped by a wave-uniform branch: no use of a
+  // loaded value sits between the loads, so they are all in flight together
   float v[kStageMax][KC];
 #pragma unroll
   for (int r = 0; r < kStageMax; ++r) {
-    const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
-                      ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
-    gptr<unsigned char> rp = (gptr<unsigned char>)((gptr<float>)base + g);
+    if (r < nrw) {
+      const int64_t g = (int64_t)(uint32_t)__builtin_amdgcn_readlane(lo, r) |
+                        ((int64_t)__builtin_amdgcn_readlane(hi, r) << 32);
+      gptr<unsigned char> rp = (gptr<unsigned char>)((gptr<float>)base + g);
 #pragma unroll
-    for (int k = 0; k < KC; ++k) v[r][k] = __builtin_nontemporal_load((gptr<float>)(rp + col[k]));
+      for (int k = 0; k < KC; ++k) v[r][k] = __builtin_nontemporal_load((gptr<float>)(rp + col[k]));
+    }
   }
   work();
   auto put = [&](auto all) {
