@@ -432,7 +432,9 @@ def test_smaller_scratch_groups_when_memory_is_short():
 
 
 def test_persistent_launch_equals_pass_launches(ctx):
-    # same tiles either way: the periodograms are bit-identical
+    # same tiles either way: the periodograms are bit-identical (the
+    # persistent launch runs the general kernel, the per-pass launches the
+    # kernels compiled for full-tile and range-tile passes)
     xs, cfgs = batch_inputs(5)
     dev_x = [dev(x) for x in xs]
     params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
