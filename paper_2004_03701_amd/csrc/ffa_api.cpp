@@ -110,7 +110,7 @@ struct Job {
   bool persistent = false;
   Tiling tiling;            // tiling the tables were built for
   int32_t max_counters = 0;
-  DevBuf series, oct, xf, scales, tiles, need;
+  DevBuf series, oct, xf, scales, tiles, need, src_rows;
   int32_t stats_blocks = 0;
 };
 
@@ -358,9 +358,12 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       std::max<int64_t>(1, (2048 + nseries - 1) / nseries), std::max<int64_t>(1, maxn / 4096));
   HIP_TRY(ctx, upload(job->series, sd), "upload series table");
   HIP_TRY(ctx, upload(job->oct, od), "upload octave table");
+  std::vector<int32_t> src_rows;
+  attach_source_rows(&tiles, xf.data(), &src_rows);
   HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
   HIP_TRY(ctx, upload(job->scales, scales), "upload scale table");
   HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
+  HIP_TRY(ctx, upload(job->src_rows, src_rows), "upload source-row table");
   HIP_TRY(ctx, upload(job->need, need), "upload dependency table");
   return FFA_OK;
 }
@@ -471,6 +474,7 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
   pa.counters = ctx->counters.as<int32_t>();
   pa.error_flag = ctx->flag.as<int32_t>();
   pa.spin_limit = 1 << 22;
+  pa.src_rows = job.src_rows.as<int32_t>();
   const TileDesc* tiles = job.tiles.as<TileDesc>();
   for (const Group& g : job.groups) {
     if (job.persistent) {
@@ -852,8 +856,11 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   }
   // per-call tables live as long as the context (kept in a small job)
   auto job = std::make_shared<Job>();
+  std::vector<int32_t> src_rows;
+  attach_source_rows(&tiles, xf.data(), &src_rows);
   HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
   HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
+  HIP_TRY(ctx, upload(job->src_rows, src_rows), "upload source-row table");
   HIP_TRY(ctx, ctx->scr0.reserve((size_t)m * p * 4 + 16), "allocate scratch");
   HIP_TRY(ctx, ctx->scr1.reserve((size_t)m * p * 4 + 16), "allocate scratch");
   PassArgs pa{};
@@ -871,6 +878,7 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   pa.scr0 = ctx->scr0.as<float>();
   pa.scr1 = ctx->scr1.as<float>();
   pa.out_rows = out;
+  pa.src_rows = job->src_rows.as<int32_t>();
   for (const Launch& l : launches) {
     pa.tiles = job->tiles.as<TileDesc>() + l.tile_off;
     pa.ntiles = l.ntiles;

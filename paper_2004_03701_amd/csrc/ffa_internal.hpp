@@ -106,11 +106,15 @@ struct TileDesc {
   // (-1: no wait) and adds one to counter `done` when finished (-1: none).
   int32_t dep;
   int32_t done;
+  // Range tiles: position in PassArgs::src_rows of their source-row list (a
+  // count, then the rows); set by attach_source_rows.
+  int32_t rows_off;
 };
 
 // Arguments of one pass launch.
 struct PassArgs {
   const TileDesc* tiles;
+  const int32_t* src_rows;  // source-row lists of the range tiles (TileDesc::rows_off)
   int32_t ntiles;
   int32_t lds_rows_cap;    // cap on the rows of a tile (0 = what fits)
   int32_t waves;           // waves per workgroup (kWavesLarge or kWavesSmall)

@@ -1263,44 +1263,39 @@ __device__ __forceinline__ void build_meta_par(Meta M, int r0, int n, int s0, in
 // Node (heap index) of level l holding position q.
 __device__ __forceinline__ int find_node(const Meta& M, int l, int q);
 
-// A range tile with one column group per lane: the node metadata (wave 0),
-// then every level's pair operations at once (all threads, LDS byte offsets
-// into `ops`, six ints each), the rows L levels below from scratch, and L
-// pair-merge levels. Needs merge_groups(p) <= 64.
+// A range tile with one column group per lane: the rows L levels below from
+// scratch (the tile's source-row list, made by the host in the order of the
+// node metadata), and while their loads are in flight the node metadata
+// (wave 0) and every level's pair operations (all threads, LDS byte offsets
+// into `ops`, six ints each); then L pair-merge levels. Needs
+// merge_groups(p) <= 64.
 template <int WV>
 __device__ __forceinline__ void range_tile_pairs(const PassArgs& a, const TileDesc& t, const XformDesc& x,
                                                  int r0, int n, int p, int stride, float* rows, int R,
-                                                 const Meta& M, int* th, int* ops) {
+                                                 const Meta& M, int* ops) {
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int L = t.levels;
   const int G = merge_groups(p);
   const int stride4 = stride * 4, p4 = p * 4;
   const int junk4 = (R + 1) * stride4, zero4 = R * stride4;
+  constexpr int kThreads = WV * 64;
+  const int32_t* srows = a.src_rows + t.rows_off;  // count, then the rows
+  const int total = srows[0];
+  const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
+  const int q_lane = wave + WV * lane;
+  int lbase[kMaxRangeLevels + 1];
+  // the source rows' loads are in flight while the metadata and the pair
+  // operations of every level are built: kThreads / 8 threads per level (a
+  // power of two, at least one per node), an equal share of them per node of
+  // the level
+  load_rows_overlap<WV>(rows, total, p, stride, src + x.scr_off,
+                        q_lane < total ? (int64_t)srows[1 + q_lane] * p : 0, [&]() {
   if (wave == 0) build_meta_par(M, r0, n, t.s0, t.s1, L);
   __syncthreads();
-  int lbase[kMaxRangeLevels + 1];
   lbase[0] = 0;
 #pragma unroll
   for (int l = 0; l < kMaxRangeLevels; ++l) lbase[l + 1] = lbase[l] + (l < L ? M.lops[l] : 0);
-  const int llast = (2 << L) - 2;
-  const int total = M.off[llast] + M.hi[llast] - M.lo[llast];
-  constexpr int kThreads = WV * 64;
-  {
-    // source rows: a fixed share of the threads per node of level L
-    const int slots = kThreads >> L;
-    const int h = (1 << L) - 1 + tid / slots;
-    const int len = M.hi[h] - M.lo[h], base = M.r0[h] + M.lo[h], off = M.off[h];
-    for (int k = tid % slots; k < len; k += slots) th[off + k] = base + k;
-  }
-  __syncthreads();
-  const float* src = (t.bufs & 1) ? a.scr1 : a.scr0;
-  const int q_lane = wave + WV * lane;
-  // the source rows' loads are in flight while the pair operations of every
-  // level are built: kThreads / 8 threads per level (a power of two, at least
-  // one per node), an equal share of them per node of the level
-  load_rows_overlap<WV>(rows, total, p, stride, src + x.scr_off,
-                        q_lane < total ? (int64_t)th[q_lane] * p : 0, [&]() {
   static_assert(kMaxRangeLevels <= 8 && (kThreads / 8) >> (kMaxRangeLevels - 1) >= 1,
                 "thread shares of the pair operations");
   constexpr int kPerLevel = kThreads / 8;
@@ -1655,8 +1650,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
       nrows = n;
       s_base = 0;
     } else {
-      range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, th,
-                           reinterpret_cast<int*>(snrbuf));
+      range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, reinterpret_cast<int*>(snrbuf));
       nrows = t.s1 - t.s0;
       s_base = t.s0;
     }
@@ -1700,8 +1694,7 @@ __device__ __forceinline__ void ffa_tile(const PassArgs& a, const TileDesc& t, c
     nrows = n;
     s_base = 0;
   } else if (JS == 1 && merge_groups(p) <= 64) {
-    range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, th,
-                         reinterpret_cast<int*>(snrbuf));
+    range_tile_pairs<WV>(a, t, x, r0, n, p, stride, rows, R, M, reinterpret_cast<int*>(snrbuf));
     nrows = t.s1 - t.s0;
     s_base = t.s0;
   } else {

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <map>
 #include <sstream>
 
 namespace ffa {
@@ -271,6 +272,81 @@ int64_t range_peak_rows(int64_t n, int64_t lo, int64_t hi, int levels) {
 }
 
 }  // namespace
+
+namespace {
+
+// Walks the nodes below a node (r0, n rows, rows [lo, hi) wanted) down to
+// `levels` levels, left child first, appending the rows wanted at the bottom.
+// The children of a merge take the head and tail rows the wanted rows read
+// (Sec. 2.2); a one-row block's tail child is the row itself.
+void source_rows_rec(int64_t r0, int64_t n, int64_t lo, int64_t hi, int l, int levels,
+                     std::vector<int32_t>* out) {
+  if (l == levels) {
+    for (int64_t k = lo; k < hi; ++k) out->push_back((int32_t)(r0 + k));
+    return;
+  }
+  if (hi <= lo || n == 0) {
+    source_rows_rec(r0, 0, 0, 0, l + 1, levels, out);
+    source_rows_rec(r0, 0, 0, 0, l + 1, levels, out);
+    return;
+  }
+  if (n == 1) {
+    source_rows_rec(r0, 0, 0, 0, l + 1, levels, out);
+    source_rows_rec(r0, 1, 0, 1, l + 1, levels, out);
+    return;
+  }
+  const int64_t mh = n / 2;
+  int64_t i0, j0, i1, j1;
+  merge_indices(n, lo, &i0, &j0);
+  merge_indices(n, hi - 1, &i1, &j1);
+  source_rows_rec(r0, mh, i0, i1 + 1, l + 1, levels, out);
+  source_rows_rec(r0 + mh, n - mh, j0, j1 + 1, l + 1, levels, out);
+}
+
+}  // namespace
+
+int32_t range_tile_source_rows(int64_t m, int d_dst, int64_t node, int64_t s0, int64_t s1,
+                               int levels, std::vector<int32_t>* out) {
+  int64_t r0, n;
+  node_geometry(m, d_dst, node, &r0, &n);
+  const size_t before = out->size();
+  source_rows_rec(r0, n, s0, s1, 0, levels, out);
+  return (int32_t)(out->size() - before);
+}
+
+void attach_source_rows(std::vector<TileDesc>* tiles, const XformDesc* xf,
+                        std::vector<int32_t>* table) {
+  struct Key {
+    int64_t m, node, s0, s1;
+    int32_t d, levels;
+    bool operator<(const Key& o) const {
+      if (m != o.m) return m < o.m;
+      if (node != o.node) return node < o.node;
+      if (s0 != o.s0) return s0 < o.s0;
+      if (s1 != o.s1) return s1 < o.s1;
+      if (d != o.d) return d < o.d;
+      return levels < o.levels;
+    }
+  };
+  std::map<Key, int32_t> seen;
+  std::vector<int32_t> rows;
+  for (TileDesc& t : *tiles) {
+    t.rows_off = -1;
+    if (t.flags & kTileFull) continue;
+    const Key k{xf[t.xf].m, t.node, t.s0, t.s1, t.d_dst, t.levels};
+    auto it = seen.find(k);
+    if (it != seen.end()) {
+      t.rows_off = it->second;
+      continue;
+    }
+    rows.clear();
+    const int32_t cnt = range_tile_source_rows(k.m, t.d_dst, t.node, t.s0, t.s1, t.levels, &rows);
+    t.rows_off = (int32_t)table->size();
+    table->push_back(cnt);
+    table->insert(table->end(), rows.begin(), rows.end());
+    seen.emplace(k, t.rows_off);
+  }
+}
 
 void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
                           int32_t levels_per_pass, bool out_rows,

@@ -80,4 +80,18 @@ int32_t width_set_of(const int32_t* widths, int32_t n);
 // Start row and size of node `node` at depth d of the m-row tree.
 void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n);
 
+// Source rows of a range tile: rows [s0, s1) of node `node` at depth d_dst of
+// the m-row tree are built from rows of its descendants `levels` levels
+// below. Appends those rows (rows of the transform) to `out` in the order
+// the tile keeps them in LDS: the descendants left to right, each one's rows
+// ascending. Returns their count.
+int32_t range_tile_source_rows(int64_t m, int d_dst, int64_t node, int64_t s0, int64_t s1,
+                               int levels, std::vector<int32_t>* out);
+
+// Sets rows_off of every range tile of `tiles` (transform table `xf`) to the
+// position in `table` of its source-row list, stored as the count followed by
+// the rows; tiles of the same geometry share one list. Full tiles get -1.
+void attach_source_rows(std::vector<TileDesc>* tiles, const XformDesc* xf,
+                        std::vector<int32_t>* table);
+
 }  // namespace ffa
