@@ -29,7 +29,8 @@ using namespace ffa;
 
 namespace {
 
-// Grow-only device buffer (pointers stay valid for captured graphs).
+// Grow-only device buffer. Growing frees the old allocation, so a buffer the
+// context owns is grown through grow(), which drops the captured graphs.
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -116,6 +117,7 @@ struct Job {
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
+  std::shared_ptr<Job> job;  // the tables the graph's launches read
   ~GraphEntry() {
     if (exec) (void)hipGraphExecDestroy(exec);
   }
@@ -181,6 +183,15 @@ ffa_status hip_fail(ffa_ctx* ctx, hipError_t e, const char* what) {
     hipError_t _e = (call);                         \
     if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
   } while (0)
+
+// Grows a context-owned device buffer. Captured graphs hold the addresses of
+// the context's buffers, so every graph is dropped when one of them moves.
+hipError_t grow(ffa_ctx* ctx, DevBuf& b, size_t n, bool zero = false) {
+  void* before = b.ptr;
+  hipError_t e = b.reserve(n, zero);
+  if (b.ptr != before) ctx->graphs.clear();
+  return e;
+}
 
 ffa_status get_plan(ffa_ctx* ctx, const ffa_search_params& a, int64_t nsamp,
                     std::shared_ptr<SeriesPlan>* out) {
@@ -297,9 +308,9 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       std::vector<std::vector<TileDesc>> passes;
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
-        plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
-                             rows_capacity(x.p, ctx->tiling),
-                             ctx->tiling.levels_per_pass, false, &passes);
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, ctx->tiling),
+                                  ctx->tiling.levels_per_pass, false, &passes))
+          return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
       }
       for (auto& ps : passes) {
         grp.passes.push_back(Launch{tiles.size(), (int32_t)ps.size()});
@@ -319,9 +330,9 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
         std::vector<std::vector<TileDesc>> passes;
-        plan_transform_tiles((int32_t)k, x.m, x.p, x.keep,
-                             rows_capacity(x.p, ctx->tiling),
-                             ctx->tiling.levels_per_pass, false, &passes);
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, ctx->tiling),
+                                  ctx->tiling.levels_per_pass, false, &passes))
+          return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
         const int64_t local = (int64_t)(k - g.xf0);
         const int32_t cbase = (int32_t)(local * kMaxPasses);
         for (int pk = 0; pk < kMaxPasses; ++pk)
@@ -384,10 +395,8 @@ ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
                          (size_t)std::max(job.max_counters, 1) * sizeof(int32_t),
                          16};
   for (int b = 0; b < 9; ++b) {
-    void* before = bufs[b]->ptr;
     // the status flag is read before anything has written it
-    HIP_TRY(ctx, bufs[b]->reserve(want[b], bufs[b] == &ctx->flag), "allocate workspace");
-    if (before && bufs[b]->ptr != before) ctx->graphs.clear();
+    HIP_TRY(ctx, grow(ctx, *bufs[b], want[b], bufs[b] == &ctx->flag), "allocate workspace");
   }
   return FFA_OK;
 }
@@ -595,6 +604,7 @@ ffa_status run_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     }
     if (ce != hipSuccess) return hip_fail(ctx, ce, "end capture");
     auto ge = std::make_shared<GraphEntry>();
+    ge->job = job;
     hipError_t ie = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return hip_fail(ctx, ie, "instantiate graph");
@@ -846,8 +856,9 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
     HIP_TRY(ctx, hipMemcpyAsync(out, in, (size_t)p * 4, hipMemcpyDeviceToDevice, st), "copy");
     return FFA_OK;
   }
-  plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling),
-                       ctx->tiling.levels_per_pass, true, &passes);
+  if (!plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling),
+                            ctx->tiling.levels_per_pass, true, &passes))
+    return fail(ctx, FFA_ERR_INVALID_ARG, "the transform's tiles do not fit the tile rows");
   std::vector<TileDesc> tiles;
   std::vector<Launch> launches;
   for (auto& ps : passes) {
@@ -861,8 +872,8 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
   HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
   HIP_TRY(ctx, upload(job->src_rows, src_rows), "upload source-row table");
-  HIP_TRY(ctx, ctx->scr0.reserve((size_t)m * p * 4 + 16), "allocate scratch");
-  HIP_TRY(ctx, ctx->scr1.reserve((size_t)m * p * 4 + 16), "allocate scratch");
+  HIP_TRY(ctx, grow(ctx, ctx->scr0, (size_t)m * p * 4 + 16), "allocate scratch");
+  HIP_TRY(ctx, grow(ctx, ctx->scr1, (size_t)m * p * 4 + 16), "allocate scratch");
   PassArgs pa{};
   pa.lds_rows_cap = ctx->tiling.lds_rows;
   pa.waves = ctx->tiling.waves;
@@ -879,9 +890,14 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
   pa.scr1 = ctx->scr1.as<float>();
   pa.out_rows = out;
   pa.src_rows = job->src_rows.as<int32_t>();
-  for (const Launch& l : launches) {
+  // rows short enough for the pair forms run the kernels compiled for them
+  // (a first pass holds full tiles only, a later pass range tiles only)
+  const bool pairs = pair_forms_fit(p);
+  for (size_t k = 0; k < launches.size(); ++k) {
+    const Launch& l = launches[k];
     pa.tiles = job->tiles.as<TileDesc>() + l.tile_off;
     pa.ntiles = l.ntiles;
+    pa.pairs_only = pairs ? (k == 0 ? 2 : 3) : 0;
     HIP_TRY(ctx, launch_pass(pa, st), "fold pass kernel");
   }
   // keep the tables alive until the work is done
@@ -902,9 +918,9 @@ ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int
   HIP_TRY(ctx, tmp.reserve(sizeof(SeriesDev)), "allocate");
   HIP_TRY(ctx, hipMemcpy(tmp.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
   const int32_t bps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2048, nsamp / 4096));
-  HIP_TRY(ctx, ctx->partials.reserve((size_t)bps * 2 * sizeof(double)), "allocate");
-  HIP_TRY(ctx, ctx->norm.reserve(2 * sizeof(float)), "allocate");
-  HIP_TRY(ctx, ctx->flag.reserve(16, true), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->partials, (size_t)bps * 2 * sizeof(double)), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->norm, 2 * sizeof(float)), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->flag, 16, true), "allocate");
   HIP_TRY(ctx, launch_stats(tmp.as<SeriesDev>(), 1, dtype, bps, ctx->partials.as<double>(),
                             stats_dev, ctx->norm.as<float>(), ctx->flag.as<int32_t>(), st),
           "stats kernels");
@@ -935,7 +951,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   HIP_TRY(ctx, t2.reserve(sizeof od), "allocate");
   HIP_TRY(ctx, hipMemcpy(t1.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
   HIP_TRY(ctx, hipMemcpy(t2.ptr, &od, sizeof od, hipMemcpyHostToDevice), "upload");
-  HIP_TRY(ctx, ctx->norm.reserve(2 * sizeof(float)), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->norm, 2 * sizeof(float)), "allocate");
   if (stats_dev)
     HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
   const int64_t nblocks = (nsamp + bs - 1) / bs;

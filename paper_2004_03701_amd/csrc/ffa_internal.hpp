@@ -168,15 +168,20 @@ enum WidthSet : int32_t {
   kWidthsDuty9 = 2,    // 1,2,3,5,8,12,19,30,48: duty cycles 0.5 % .. 20 % of 240 bins
 };
 
+// Rows short enough for the pair-merge forms: one column group per lane, and
+// room in the wave for the register levels of full tiles. Raw-transform
+// launches (no S/N) of such rows run the kernels compiled for those forms.
 // Launches in which every tile takes the pair-merge forms (one column group
 // per lane, register levels in full tiles) and the register-window S/N of a
 // compiled width grid: rows of 160 .. max bins with one column group per lane
 // (the S/N window of 32 starts plus the widest boxcar then fits in a row and
 // its copied bins, and the partial maxima fit in the row area of any tile of
 // two or more rows). Such launches run a kernel compiled for those forms only.
+inline __host__ __device__ bool pair_forms_fit(int max_p) {
+  return col_iters(max_p) == 1 && merge_groups(max_p) + kRegLevels <= 64;
+}
 inline __host__ __device__ bool pairs_only_launch(int min_p, int max_p, int width_set) {
-  return width_set != kWidthsGeneral && min_p >= 160 && col_iters(max_p) == 1 &&
-         merge_groups(max_p) + kRegLevels <= 64;
+  return width_set != kWidthsGeneral && min_p >= 160 && pair_forms_fit(max_p);
 }
 
 }  // namespace ffa

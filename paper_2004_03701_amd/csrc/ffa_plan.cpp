@@ -348,10 +348,11 @@ void attach_source_rows(std::vector<TileDesc>* tiles, const XformDesc* xf,
   }
 }
 
-void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
+bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
                           int32_t levels_per_pass, bool out_rows,
                           std::vector<std::vector<TileDesc>>* passes) {
   (void)p;
+  if (rows_cap < 2) return false;
   auto pass = [&](size_t k) -> std::vector<TileDesc>& {
     if (passes->size() <= k) passes->resize(k + 1);
     return (*passes)[k];
@@ -360,7 +361,7 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
   if (m <= rows_cap) {
     TileDesc t{xf, 0, 0, m, 0, 0, (uint8_t)(kTileFull | fin), 0, -1, -1};
     pass(0).push_back(t);
-    return;
+    return true;
   }
   // bottom depth: the shallowest whose nodes fit in LDS
   int db = 0;
@@ -372,7 +373,10 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
                -1, -1};
     pass(0).push_back(t);
   }
-  const int L = std::max(1, std::min<int>(levels_per_pass, kMaxRangeLevels));
+  // one output row of an L-level range tile reads up to 2^L rows at the
+  // bottom level, so the levels of a pass are capped where 2^L <= rows_cap
+  int L = std::max(1, std::min<int>(levels_per_pass, kMaxRangeLevels));
+  while (L > 1 && (1 << L) > rows_cap) --L;
   const int npu = (db + L - 1) / L;
   int d_src = db;
   for (int k = 0; k < npu; ++k) {
@@ -386,6 +390,7 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
       const int64_t end = last ? keep : n;
       int64_t s0 = 0;
       while (s0 < end) {
+        if (range_peak_rows(n, s0, s0 + 1, lv) > rows_cap) return false;
         // largest s1 whose rows fit at every level of the pass
         int64_t lo = s0 + 1, hi = end;
         while (lo < hi) {
@@ -403,6 +408,7 @@ void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
     }
     d_src = d_dst;
   }
+  return true;
 }
 
 }  // namespace ffa

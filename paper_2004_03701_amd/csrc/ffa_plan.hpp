@@ -60,8 +60,10 @@ struct Tiling {
 int32_t rows_capacity(int32_t p, const Tiling& t);
 
 // Tiles of one transform, grouped by pass. `xf` is the transform's index in
-// the launch's transform table. Appends to passes[k] for pass k.
-void plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
+// the launch's transform table. Appends to passes[k] for pass k. The levels of
+// a range pass are capped so that every tile's rows fit rows_cap at every
+// level; returns false (and the plan must not be used) if some tile would not.
+bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
                           int32_t levels_per_pass, bool out_rows,
                           std::vector<std::vector<TileDesc>>* passes);
 

@@ -47,6 +47,8 @@ TRANSFORM_SHAPES = [
     (1, 7), (2, 2), (2, 3), (3, 5), (5, 17), (8, 6), (37, 128), (64, 255), (100, 259),
     (129, 259), (130, 259), (131, 259), (257, 240), (1000, 251), (1073, 259), (1310, 200),
     (2048, 128), (3001, 97), (12000, 33), (500, 1000), (300, 1280), (41, 2),
+    # wide rows whose tiles hold few rows: the range passes take fewer levels
+    (200, 1280), (500, 600), (497, 519),
 ]
 
 
@@ -539,3 +541,113 @@ def test_autotune_uneven_batch_and_cache(ctx, tmp_path):
     ref_o = oracle.search(xs[i], cfgs[i].tsamp, cfgs[i].period_min, cfgs[i].period_max,
                           cfgs[i].bins_min, cfgs[i].bins_max, cfgs[i].widths)
     assert snr_close(got.cpu().numpy()[offs[i]:offs[i] + ref_o.snr.shape[0]], ref_o.snr) < SNR_RTOL
+
+
+# ---------------------------------------------------------------------------
+# The forms that run in the benchmark, against the oracle
+# ---------------------------------------------------------------------------
+
+def test_pair_kernels_integer_search_bit_exact(ctx):
+    # The kernels compiled for the pair-merge forms and the register-window S/N
+    # (every p >= 160, the duty-cycle width grid): ds = 1 (P_min = 240 tau,
+    # one pseudo-octave: P_max = 259.5 tau stops the search before the second,
+    # whose factor 260/240 is not an integer), no normalisation, integer samples with
+    # |x| <= 8, so every merge and prefix sum is an exact FP32 integer
+    # (m (p + 48) 8 < 2^24). Transforms of 772..833 rows take a full-tile pass
+    # and a range pass. The S/N is then the exact best boxcar sum times the
+    # FP32 scale 1/sqrt(m w), rounded once.
+    n = 200_000
+    x = np.random.default_rng(31).integers(-8, 9, size=n).astype(np.float32)
+    widths = synth.WIDTHS_DUTY
+    prm = ffa.make_params(1.0, 240.0, 259.5, 240, 259, widths, normalise=False)
+    per, bins, snr = ffa.ffa_search(ctx, dev(x), prm)
+    torch.cuda.synchronize()
+    got = snr.cpu().numpy()
+    ref = oracle.search(x, 1.0, 240.0, 259.5, 240, 259, widths, normalise=False)
+    assert np.array_equal(per, ref.periods) and np.array_equal(bins, ref.bins)
+    assert (ref.octave == 0).all() and ref.rows_m.min() > 64 and ref.rows_m.max() * (259 + 48) * 8 < 2 ** 24
+    w = np.asarray(widths, dtype=np.float64)[None, :]
+    mw = ref.rows_m.astype(np.float64)[:, None] * w
+    best = np.rint(ref.snr * np.sqrt(mw))
+    assert np.allclose(best, ref.snr * np.sqrt(mw), rtol=0, atol=1e-6)
+    scale = (1.0 / np.sqrt(mw)).astype(np.float32)
+    want = best.astype(np.float32) * scale
+    assert want.dtype == np.float32
+    assert np.array_equal(got, want)
+
+
+def _workload3_pair():
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    idx = [int(pulsed[0]), 2]
+    xs = [synth.workload3_series(i, pulsed=pulsed)[0] for i in idx]
+    refs = [oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                          cfg.bins_max, cfg.widths) for x in xs]
+    prm = [ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
+                           cfg.bins_max, cfg.widths) for _ in xs]
+    return xs, prm, np.concatenate([r.snr for r in refs])
+
+
+def test_persistent_and_graph_forms_match_oracle(ctx):
+    # two full-size workload-3 series, every row against the oracle: one
+    # persistent launch per group, eager and replayed from a hipGraph, and the
+    # per-pass launches replayed from a hipGraph
+    xs, prm, ref = _workload3_pair()
+    series = [dev(x) for x in xs]
+    for persistent in (True, False):
+        ffa.ffa_set_tiling(ctx, 0, 5, persistent=persistent)
+        try:
+            if persistent:
+                print("persistent launch, eager", flush=True)
+                got, offs = ffa.ffa_search_batch(ctx, series, prm)
+                torch.cuda.synchronize()
+                assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+                assert snr_close(got.cpu().numpy(), ref) < SNR_RTOL
+            print(f"graph replays, persistent={persistent}", flush=True)
+            offs = [0, int(ffa.ffa_plan_rows(prm[0], xs[0].size))]
+            out = torch.full((ref.shape[0], ref.shape[1]), -1.0, device="cuda")
+            for rep in range(3):
+                out.fill_(-1.0)
+                ffa.ffa_search_batch(ctx, series, prm, snr=out, row_offset=offs, use_graph=True)
+                torch.cuda.synchronize()
+                assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+                assert snr_close(out.cpu().numpy(), ref) < SNR_RTOL, rep
+                # eager work of the program between replays
+                ffa.ffa_search_batch(ctx, series[:1], prm[:1])
+                torch.cuda.synchronize()
+        finally:
+            ffa.ffa_set_tiling(ctx)
+
+
+def test_graph_replay_after_context_buffers_move(ctx):
+    # a replayed graph must not keep the addresses of context buffers that a
+    # later call has reallocated (a raw transform growing the scratch, an
+    # autotune dropping the cached tables)
+    xs, cfgs = batch_inputs(3)
+    dev_x = [dev(x) for x in xs]
+    params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY) for t, lo, hi in cfgs]
+    eager, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    eager = eager.cpu().numpy()
+    out = torch.full(eager.shape, -1.0, device="cuda")
+    ffa.ffa_search_batch(ctx, dev_x, params, snr=out, row_offset=offs, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), eager)
+    # a raw transform far larger than the batch's scratch: the scratch moves
+    X = np.random.default_rng(5).integers(-8, 9, size=(20000, 259)).astype(np.float32)
+    big = ffa.ffa_transform(ctx, dev(X))
+    torch.cuda.synchronize()
+    del big
+    out.fill_(-1.0)
+    ffa.ffa_search_batch(ctx, dev_x, params, snr=out, row_offset=offs, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), eager)
+    # the job tables are dropped and rebuilt by an autotune
+    try:
+        ffa.ffa_autotune(ctx, dev_x[:1], params[:1])
+    finally:
+        ffa.ffa_set_tiling(ctx)
+    out.fill_(-1.0)
+    ffa.ffa_search_batch(ctx, dev_x, params, snr=out, row_offset=offs, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), eager)

@@ -83,3 +83,15 @@ def test_sub_range_errors(ctx):
     with pytest.raises(ffa.FFAError) as e:
         ffa.ffa_search_ranges(ctx, x, good, snr=small)
     assert e.value.status == ffa.FFA_ERR_BUFFER_TOO_SMALL
+
+
+def test_sub_ranges_with_about_a_thousand_bins(ctx):
+    # long periods at about 1000 bins on a full-length series: transforms of
+    # a few hundred rows of ~1000 bins, whose tiles hold only 14 rows, so the
+    # range passes are capped at 3 levels (a 5-level tile would need 32 rows)
+    cfg = synth.workload3_config()
+    pulsed = synth.workload3_pulsed()
+    x, _ = synth.workload3_series(int(pulsed[1]), pulsed=pulsed)
+    per, _ = run_and_compare(ctx, x, cfg.tsamp, [(0.5, 2.0, 240, 259), (2.0, 10.0, 960, 1039)],
+                             cfg.widths, True)
+    assert per.size > 0

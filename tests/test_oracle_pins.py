@@ -422,3 +422,46 @@ def test_sub_ranges_resolve_a_narrow_pulse_better():
     with pytest.raises(oracle.PlanError):
         oracle.search_ranges(x, 1.0, [(128.0, 300.0, 128, 255), (256.0, 1024.0, 256, 511)],
                              widths, normalise=False)
+
+
+# --------------------------------------------------------------------------
+# Normalisation (Sec. 5.2): zero mean and unit standard deviation of the whole
+# raw series, before any downsampling (reading c13: population std, FP64)
+# --------------------------------------------------------------------------
+
+def test_normalise_stats_hand_values():
+    # [1, 2, 3, 4]: mean 2.5, squared deviations 2.25 + 0.25 + 0.25 + 2.25 = 5,
+    # population variance 5 / 4 = 1.25 (the sample variance would be 5 / 3)
+    mu, sigma = oracle.normalise_stats(np.array([1.0, 2.0, 3.0, 4.0]))
+    assert mu == 2.5
+    assert sigma == math.sqrt(1.25)
+    # a constant offset and a scale pass straight through
+    mu, sigma = oracle.normalise_stats(np.array([-7.0, 13.0]))
+    assert (mu, sigma) == (3.0, 10.0)
+
+
+def test_search_normalise_hand_worked_snr():
+    # Raw period of 16 samples: two samples of height h, fourteen of c. Zero
+    # mean needs 2h + 14c = 0 (c = -h/7); unit population variance needs
+    # (2h^2 + 14c^2)/16 = h^2/7 = 1, so h = sqrt(7). The series given to the
+    # search is 5 + 3 z, so normalising must recover z exactly in form.
+    # Plan (tsamp 1, P 16..17, 8 bins): ds0 = 16/8 = 2, an integer factor, so
+    # the downsampled series is the pair sums [2h, 2c, ..., 2c] with noise
+    # variance 2 (App. A.4), and the one transform has p = 8, m = N/16 rows.
+    # Row s = 0 does not drift: bin 0 sums to 2hm and the other bins to 2cm.
+    #   width 1: 2hm / sqrt(2m) = sqrt(14 m)
+    #   width 2: (2h + 2c) m / sqrt(2 * 2m) = (h + c) sqrt(m) = sqrt(36 m / 7)
+    # Normalising after downsampling, or by the sample std, gives other values.
+    m = 10
+    h = math.sqrt(7.0)
+    c = -h / 7.0
+    period = np.array([h, h] + [c] * 14)
+    z = np.tile(period, m)
+    x = 5.0 + 3.0 * z
+    res = oracle.search(x, 1.0, 16.0, 17.0, 8, 8, (1, 2), normalise=True)
+    assert res.periods[0] == 16.0 and res.bins[0] == 8 and res.rows_m[0] == m
+    assert res.snr[0, 0] == pytest.approx(math.sqrt(14.0 * m), rel=1e-12)
+    assert res.snr[0, 1] == pytest.approx(math.sqrt(36.0 * m / 7.0), rel=1e-12)
+    # the same series already normalised gives the same periodogram
+    res0 = oracle.search(z, 1.0, 16.0, 17.0, 8, 8, (1, 2), normalise=False)
+    assert np.allclose(res.snr, res0.snr, rtol=1e-12, atol=1e-12)
