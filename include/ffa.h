@@ -136,6 +136,31 @@ ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* se
                             const int64_t* row_offset, float* snr_dev, int64_t capacity_rows,
                             int32_t use_graph, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): ffa_search with no
+ * device allocation of its own. Arguments, outputs and errors as ffa_search.
+ * Every intermediate buffer (the tables of the search, the statistics, the
+ * downsampled series and the scratch rows between passes) is carved from a
+ * static device workspace of FFA_NOALLOC_WORKSPACE_BYTES that each device the
+ * library runs on holds until the process ends; the call allocates no device
+ * memory, but it waits for `stream` once, after copying its tables into the
+ * workspace and before queueing its kernels. Limits: the series' tables and
+ * downsampled samples plus two scratch buffers, each holding the largest
+ * transform's m * p floats, must fit the workspace (a 2^23-sample series over
+ * 0.5 - 10 s at 64 us and 240 - 259 bins does, with room to spare); otherwise
+ * FFA_ERR_INVALID_ARG with a message, and nothing is queued. The tiling is the
+ * context's with per-pass launches (its persistent flag is ignored).
+ * All calls on one device share the workspace, which keeps the last call's
+ * contents: calls that overlap on one device (other streams, other threads,
+ * other contexts) race and must not be made. The workspace's status word is
+ * cleared by each call; ffa_sync_status reports a degenerate series of the
+ * latest call. */
+#define FFA_NOALLOC_WORKSPACE_BYTES (128u << 20)
+ffa_status ffa_search_noalloc(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                              const ffa_search_params* params, double* period_host,
+                              int32_t* bins_host, float* snr_dev, int64_t capacity_rows,
+                              void* stream);
+
 /* Dynamic duty-cycle resolution (Sec. 5.6): the period range of one series
  * split into nranges consecutive sub-ranges, each searched with its own
  * parameters (typically more phase bins at longer periods), the periodograms

@@ -36,7 +36,10 @@ EXPORTED = (
     "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
     "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
     "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch", "ffa_search_ranges",
+    "ffa_search_noalloc",
 )
+
+FFA_NOALLOC_WORKSPACE_BYTES = 128 << 20
 
 
 class ffa_search_params(ctypes.Structure):
@@ -126,6 +129,7 @@ def lib() -> ctypes.CDLL:
         "ffa_plan_rows": ([pp, i64, P(i64)], i32),
         "ffa_plan_export": ([pp, i64, vp, vp, vp, vp, vp, vp, i64], i32),
         "ffa_search": ([vp, vp, i64, pp, vp, vp, vp, i64, vp], i32),
+        "ffa_search_noalloc": ([vp, vp, i64, pp, vp, vp, vp, i64, vp], i32),
         "ffa_search_batch": ([vp, i32, P(vp), P(i64), pp, P(i64), vp, i64, i32, vp], i32),
         "ffa_transform": ([vp, vp, i32, i32, vp, vp], i32),
         "ffa_series_stats": ([vp, vp, i64, i32, vp, vp], i32),
@@ -233,6 +237,25 @@ def ffa_search(ctx, series, params: ffa_search_params, snr=None, stream=None,
                           per.ctypes.data if want_labels else None,
                           bins.ctypes.data if want_labels else None,
                           snr.data_ptr(), snr.shape[0], _stream(stream))
+    _check(st, ctx)
+    return per, bins, snr
+
+
+def ffa_search_noalloc(ctx, series, params: ffa_search_params, snr, stream=None,
+                       want_labels: bool = True):
+    """ffa_search in the library's static device workspace: no device memory
+    is allocated by the call. `snr` (a device tensor rows x num_widths, float32)
+    is required. Returns (periods, bins, snr)."""
+    nsamp = series.numel()
+    per = bins = None
+    if want_labels:
+        rows = ffa_plan_rows(params, nsamp)
+        per = np.empty(rows, np.float64)
+        bins = np.empty(rows, np.int32)
+    st = lib().ffa_search_noalloc(ctx, series.data_ptr(), nsamp, ctypes.byref(params),
+                                  per.ctypes.data if want_labels else None,
+                                  bins.ctypes.data if want_labels else None,
+                                  snr.data_ptr(), snr.shape[0], _stream(stream))
     _check(st, ctx)
     return per, bins, snr
 

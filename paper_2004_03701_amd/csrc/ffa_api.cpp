@@ -115,6 +115,57 @@ struct Job {
   int32_t stats_blocks = 0;
 };
 
+// Host copies of a job's device tables, before they are placed on the device.
+struct HostTables {
+  std::vector<SeriesDev> sd;
+  std::vector<OctaveDev> od;
+  std::vector<XformDesc> xf;
+  std::vector<float> scales;
+  std::vector<TileDesc> tiles;
+  std::vector<int32_t> src_rows, need;
+};
+
+// Device addresses of a job's tables (in the job's own buffers, or in a
+// caller-provided workspace).
+struct JobTables {
+  const SeriesDev* series = nullptr;
+  const OctaveDev* oct = nullptr;
+  const XformDesc* xf = nullptr;
+  const float* scales = nullptr;
+  const TileDesc* tiles = nullptr;
+  const int32_t* src_rows = nullptr;
+  const int32_t* need = nullptr;
+};
+
+// Device workspace a job's launches use besides its tables.
+struct Workspace {
+  void* ds = nullptr;          // downsampled series (FP32)
+  float* scr0 = nullptr;       // scratch rows between passes, ping-pong
+  float* scr1 = nullptr;
+  double* stats = nullptr;     // 2 doubles per series
+  float* norm = nullptr;       // 2 floats per series
+  double* partials = nullptr;  // statistics partial sums
+  int32_t* flag = nullptr;     // status word
+  int32_t* counters = nullptr; // persistent launches: completion counters
+  int32_t* ticket = nullptr;   // and the tile ticket
+};
+
+}  // namespace
+
+struct NaJob {
+  std::unique_ptr<Job> job;          // metadata; its device buffers stay empty
+  std::vector<unsigned char> packed; // the status word's 256 bytes (not copied), then the
+                                     // tables, each at a 256-byte boundary; offsets are
+                                     // from the start of the workspace
+  size_t off_series = 0, off_oct = 0, off_xf = 0, off_scales = 0, off_tiles = 0,
+         off_src_rows = 0;
+  // workspace layout past the tables
+  size_t off_stats = 0, off_norm = 0, off_flag = 0, off_partials = 0, off_ds = 0,
+         off_scr0 = 0, off_scr1 = 0;
+};
+
+namespace {
+
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   std::shared_ptr<Job> job;  // the tables the graph's launches read
@@ -135,6 +186,11 @@ struct PeakPlan {
   std::vector<double> seg_x;  // log of the segment's centre frequency
   int32_t max_seg = 0;        // rows of the largest segment
 };
+
+// A job of ffa_search_noalloc: its tables packed into one host block that a
+// call copies to the start of the static workspace, and where the rest of
+// the workspace goes.
+struct NaJob;
 
 struct TimedLaunch {
   int kind;  // 0 stats, 1 downsample, 2 fold, 3 peak detection
@@ -162,6 +218,9 @@ struct ffa_ctx {
   std::string pk_key;    // batch the peak-detection tables were uploaded for
   int32_t pk_max_nseg = 0, pk_max_seg = 0, pk_nmid = 0, pk_nbig = 0;
   int num_cus = 256;
+  void* na_ws = nullptr;         // static workspace of ffa_search_noalloc on this device
+  bool na_used = false;          // its status word has been written
+  std::map<std::string, std::shared_ptr<NaJob>> na_jobs;
   size_t scratch_budget_cells = size_t(1) << 32;  // floats per scratch buffer (16 GiB); a
                                                   // call that cannot allocate it lowers it
 };
@@ -222,22 +281,25 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v) {
   return hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Builds the device tables of a batch of series. Series pointers are stored
-// in the tables, so the job is keyed by them too.
+// Builds the tables of a batch of series on the host: transforms grouped so
+// that a group's intermediate rows fit `budget_cells` floats per scratch
+// buffer (a transform larger than that forms a group of its own). Series
+// pointers are stored in the tables, so a job is keyed by them too.
 ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
                      const int64_t* nsamp, const ffa_search_params* params,
                      const int64_t* row_offset, const std::vector<std::shared_ptr<SeriesPlan>>& plans,
-                     Job* job) {
+                     size_t budget_cells, const Tiling& tiling, Job* job, HostTables* ht) {
   job->nseries = nseries;
-  job->tiling = ctx->tiling;
+  job->tiling = tiling;
   job->dtype = params[0].dtype;
   job->num_widths = params[0].num_widths;
   for (int q = 0; q < job->num_widths; ++q) job->widths[q] = params[0].widths[q];
   job->wmax = job->widths[job->num_widths - 1];
-  std::vector<SeriesDev> sd(nseries);
-  std::vector<OctaveDev> od;
-  std::vector<XformDesc> xf;
-  std::vector<float> scales;
+  std::vector<SeriesDev>& sd = ht->sd;
+  std::vector<OctaveDev>& od = ht->od;
+  std::vector<XformDesc>& xf = ht->xf;
+  std::vector<float>& scales = ht->scales;
+  sd.assign(nseries, SeriesDev{});
   int64_t ds_off = 0, chunk = 0;
   job->ds_lds_floats = 0;
   // transforms grouped so that each group's scratch fits the budget
@@ -268,12 +330,18 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     if (a.normalise) job->any_normalise = true;
     chunk += (nsamp[i] + sd[i].block - 1) / sd[i].block;
     for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
-    if ((size_t)(gcells + pl.cells) > ctx->scratch_budget_cells && gcells > 0) {
+    // a series that fits a group stays in one; a larger one is split
+    if ((size_t)(gcells + pl.cells) > budget_cells && gcells > 0) {
       spans.push_back(GroupSpan{gx0, xf.size(), gcells});
       gx0 = xf.size();
       gcells = 0;
     }
     for (const Transform& t : pl.tr) {
+      if ((size_t)(gcells + (int64_t)t.m * t.p) > budget_cells && gcells > 0) {
+        spans.push_back(GroupSpan{gx0, xf.size(), gcells});
+        gx0 = xf.size();
+        gcells = 0;
+      }
       XformDesc x;
       x.in_off = ds_off + pl.oct[t.octave].ds_off;
       x.scr_off = gcells;
@@ -298,18 +366,18 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   spans.push_back(GroupSpan{gx0, xf.size(), gcells});
   job->ds_total = ds_off;
   job->ds_blocks = chunk;
-  std::vector<TileDesc> tiles;
-  std::vector<int32_t> need;
+  std::vector<TileDesc>& tiles = ht->tiles;
+  std::vector<int32_t>& need = ht->need;
   job->scr_cells = 0;
-  job->persistent = ctx->tiling.persistent != 0;
+  job->persistent = tiling.persistent != 0;
   for (const GroupSpan& g : spans) {
     Group grp;
     if (!job->persistent) {
       std::vector<std::vector<TileDesc>> passes;
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
-        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, ctx->tiling),
-                                  ctx->tiling.levels_per_pass, false, &passes))
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, tiling),
+                                  tiling.levels_per_pass, false, &passes))
           return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
       }
       for (auto& ps : passes) {
@@ -330,8 +398,8 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
         std::vector<std::vector<TileDesc>> passes;
-        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, ctx->tiling),
-                                  ctx->tiling.levels_per_pass, false, &passes))
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, tiling),
+                                  tiling.levels_per_pass, false, &passes))
           return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
         const int64_t local = (int64_t)(k - g.xf0);
         const int32_t cbase = (int32_t)(local * kMaxPasses);
@@ -367,16 +435,46 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   for (int i = 0; i < nseries; ++i) maxn = std::max(maxn, nsamp[i]);
   job->stats_blocks = (int32_t)std::min<int64_t>(
       std::max<int64_t>(1, (2048 + nseries - 1) / nseries), std::max<int64_t>(1, maxn / 4096));
-  HIP_TRY(ctx, upload(job->series, sd), "upload series table");
-  HIP_TRY(ctx, upload(job->oct, od), "upload octave table");
-  std::vector<int32_t> src_rows;
-  attach_source_rows(&tiles, xf.data(), &src_rows);
-  HIP_TRY(ctx, upload(job->xf, xf), "upload transform table");
-  HIP_TRY(ctx, upload(job->scales, scales), "upload scale table");
-  HIP_TRY(ctx, upload(job->tiles, tiles), "upload tile table");
-  HIP_TRY(ctx, upload(job->src_rows, src_rows), "upload source-row table");
-  HIP_TRY(ctx, upload(job->need, need), "upload dependency table");
+  attach_source_rows(&tiles, xf.data(), &ht->src_rows);
   return FFA_OK;
+}
+
+// Places a job's tables in its own device buffers.
+ffa_status upload_job(ffa_ctx* ctx, Job* job, const HostTables& ht) {
+  HIP_TRY(ctx, upload(job->series, ht.sd), "upload series table");
+  HIP_TRY(ctx, upload(job->oct, ht.od), "upload octave table");
+  HIP_TRY(ctx, upload(job->xf, ht.xf), "upload transform table");
+  HIP_TRY(ctx, upload(job->scales, ht.scales), "upload scale table");
+  HIP_TRY(ctx, upload(job->tiles, ht.tiles), "upload tile table");
+  HIP_TRY(ctx, upload(job->src_rows, ht.src_rows), "upload source-row table");
+  HIP_TRY(ctx, upload(job->need, ht.need), "upload dependency table");
+  return FFA_OK;
+}
+
+JobTables job_tables(const Job& job) {
+  JobTables t;
+  t.series = job.series.as<SeriesDev>();
+  t.oct = job.oct.as<OctaveDev>();
+  t.xf = job.xf.as<XformDesc>();
+  t.scales = job.scales.as<float>();
+  t.tiles = job.tiles.as<TileDesc>();
+  t.src_rows = job.src_rows.as<int32_t>();
+  t.need = job.need.as<int32_t>();
+  return t;
+}
+
+Workspace ctx_workspace(ffa_ctx* ctx) {
+  Workspace w;
+  w.ds = ctx->ds_buf.ptr;
+  w.scr0 = ctx->scr0.as<float>();
+  w.scr1 = ctx->scr1.as<float>();
+  w.stats = ctx->stats.as<double>();
+  w.norm = ctx->norm.as<float>();
+  w.partials = ctx->partials.as<double>();
+  w.flag = ctx->flag.as<int32_t>();
+  w.counters = ctx->counters.as<int32_t>();
+  w.ticket = ctx->ticket.as<int32_t>();
+  return w;
 }
 
 // Grows the context workspace for a job. Captured graphs hold the old
@@ -436,60 +534,57 @@ struct TimedScope {
   }
 };
 
-// Queues the device work of a job.
-ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, bool timed) {
-  ffa_status rst = reserve_job(ctx, job);
-  if (rst != FFA_OK) return rst;
+// Queues the device work of a job whose tables and workspace are in place.
+ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const Workspace& ws,
+                        float* snr, hipStream_t stream, bool timed) {
   if (timed) {
     ctx->times.profiles += job.rows;
     ctx->times.folded_cells += job.cells;
     ctx->times.input_samples += job.input_samples;
     ctx->times.downsampled_samples += job.ds_total;
   }
-  const SeriesDev* sd = job.series.as<SeriesDev>();
+  const SeriesDev* sd = tb.series;
   if (job.any_normalise) {
     TimedScope ts(ctx, 0, stream, timed);
-    HIP_TRY(ctx, launch_stats(sd, job.nseries, job.dtype, job.stats_blocks,
-                              ctx->partials.as<double>(), ctx->stats.as<double>(),
-                              ctx->norm.as<float>(), ctx->flag.as<int32_t>(), stream),
+    HIP_TRY(ctx, launch_stats(sd, job.nseries, job.dtype, job.stats_blocks, ws.partials, ws.stats,
+                              ws.norm, ws.flag, stream),
             "stats kernels");
   }
   {
   TimedScope ts(ctx, 1, stream, timed);
-  HIP_TRY(ctx, launch_downsample(sd, job.nseries, job.oct.as<OctaveDev>(), ctx->norm.as<float>(),
-                                 job.dtype, ctx->ds_buf.ptr, FFA_F32, job.ds_blocks,
-                                 job.ds_lds_floats, stream),
+  HIP_TRY(ctx, launch_downsample(sd, job.nseries, tb.oct, ws.norm, job.dtype, ws.ds, FFA_F32,
+                                 job.ds_blocks, job.ds_lds_floats, stream),
           "downsample kernel");
   }
   PassArgs pa{};
   pa.lds_rows_cap = job.tiling.lds_rows;
   pa.waves = job.tiling.waves;
-  pa.xf = job.xf.as<XformDesc>();
-  pa.in = ctx->ds_buf.ptr;
+  pa.xf = tb.xf;
+  pa.in = ws.ds;
   pa.in_dtype = FFA_F32;
   pa.num_widths = job.num_widths;
-  pa.scr0 = ctx->scr0.as<float>();
-  pa.scr1 = ctx->scr1.as<float>();
+  pa.scr0 = ws.scr0;
+  pa.scr1 = ws.scr1;
   pa.out_rows = nullptr;
   pa.snr = snr;
-  pa.scales = job.scales.as<float>();
+  pa.scales = tb.scales;
   for (int q = 0; q < kMaxWidths; ++q) pa.widths[q] = job.widths[q];
   pa.wmax = job.wmax;
   pa.max_p = job.max_p;
   pa.width_set = width_set_of(job.widths, job.num_widths);
   const bool pairs = pairs_only_launch(job.min_p, job.max_p, pa.width_set);
   set_schedules(ctx, &pa);
-  pa.ticket = ctx->ticket.as<int32_t>();
-  pa.counters = ctx->counters.as<int32_t>();
-  pa.error_flag = ctx->flag.as<int32_t>();
+  pa.ticket = ws.ticket;
+  pa.counters = ws.counters;
+  pa.error_flag = ws.flag;
   pa.spin_limit = 1 << 22;
-  pa.src_rows = job.src_rows.as<int32_t>();
-  const TileDesc* tiles = job.tiles.as<TileDesc>();
+  pa.src_rows = tb.src_rows;
+  const TileDesc* tiles = tb.tiles;
   for (const Group& g : job.groups) {
     if (job.persistent) {
       pa.tiles = tiles + g.persist.tile_off;
       pa.ntiles = g.persist.ntiles;
-      pa.need = job.need.as<int32_t>() + g.need_off;
+      pa.need = tb.need + g.need_off;
       TimedScope ts(ctx, 2, stream, timed);
       HIP_TRY(ctx, launch_persist(pa, g.ncounters, ctx->num_cus * (kWavesLarge / job.tiling.waves),
                                   stream),
@@ -507,6 +602,13 @@ ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, b
     }
   }
   return FFA_OK;
+}
+
+// Queues the device work of a job in the context's workspace.
+ffa_status enqueue_job(ffa_ctx* ctx, Job& job, float* snr, hipStream_t stream, bool timed) {
+  ffa_status rst = reserve_job(ctx, job);
+  if (rst != FFA_OK) return rst;
+  return enqueue_work(ctx, job, job_tables(job), ctx_workspace(ctx), snr, stream, timed);
 }
 
 std::string job_key(int32_t nseries, const void* const* series, const int64_t* nsamp,
@@ -562,7 +664,11 @@ ffa_status run_batch(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     } else {
       if (ctx->jobs.size() > 64) ctx->jobs.clear();
       job = std::make_shared<Job>();
-      st = build_job(ctx, nseries, series, nsamp, params, row_offset, plans, job.get());
+      HostTables ht;
+      st = build_job(ctx, nseries, series, nsamp, params, row_offset, plans,
+                     ctx->scratch_budget_cells, ctx->tiling, job.get(), &ht);
+      if (st != FFA_OK) return st;
+      st = upload_job(ctx, job.get(), ht);
       if (st != FFA_OK) return st;
       ctx->jobs[key] = job;
     }
@@ -665,6 +771,80 @@ void expand_poly(const PeakFitDev& f, int degree, double* out) {
   }
 }
 
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T>
+void pack_table(std::vector<unsigned char>* out, size_t* off, const std::vector<T>& v) {
+  *off = align256(out->size());
+  out->resize(*off + std::max<size_t>(v.size() * sizeof(T), 16), 0);
+  if (!v.empty()) memcpy(out->data() + *off, v.data(), v.size() * sizeof(T));
+}
+
+// Plans a search of one series inside the static workspace: the tables first
+// (after the status word), then statistics, the downsampled series, and two
+// scratch buffers sharing what is left, the transforms grouped to fit them.
+ffa_status build_na_job(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                        const ffa_search_params& a, const std::shared_ptr<SeriesPlan>& plan,
+                        NaJob* nj) {
+  std::vector<std::shared_ptr<SeriesPlan>> plans{plan};
+  const int64_t zero = 0;
+  Tiling tiling = ctx->tiling;
+  tiling.persistent = 0;  // per-pass launches: no counters in the workspace
+  int64_t largest = 0;
+  for (const Transform& t : plan->tr) largest = std::max<int64_t>(largest, (int64_t)t.m * t.p);
+  // tables and fixed parts do not depend on the grouping: size them with
+  // every transform in one group, then group for the space that remains
+  size_t budget = size_t(1) << 40;
+  for (int round = 0; round < 2; ++round) {
+    if (round == 1) {
+      const size_t fixed = nj->off_scr0;
+      std::ostringstream msg;
+      msg << "ffa_search_noalloc: ";
+      if (fixed + 2 * 512 >= kNoAllocBytes) {
+        msg << "the series' tables and downsampled samples (" << fixed
+            << " bytes) exceed the static workspace of " << kNoAllocBytes << " bytes; use ffa_search";
+        return fail(ctx, FFA_ERR_INVALID_ARG, msg.str());
+      }
+      budget = ((kNoAllocBytes - fixed) / 2 - 512) / 4;
+      if ((int64_t)budget < largest) {
+        msg << "a transform's " << largest << " intermediate cells exceed the " << budget
+            << " left per scratch buffer in the static workspace of " << kNoAllocBytes
+            << " bytes; use ffa_search";
+        return fail(ctx, FFA_ERR_INVALID_ARG, msg.str());
+      }
+    }
+    nj->job.reset(new Job());
+    HostTables ht;
+    ffa_status st = build_job(ctx, 1, &series, &nsamp, &a, &zero, plans, budget, tiling,
+                              nj->job.get(), &ht);
+    if (st != FFA_OK) return st;
+    const Job& job = *nj->job;
+    nj->packed.assign(kNoAllocHeader, 0);
+    pack_table(&nj->packed, &nj->off_series, ht.sd);
+    pack_table(&nj->packed, &nj->off_oct, ht.od);
+    pack_table(&nj->packed, &nj->off_xf, ht.xf);
+    pack_table(&nj->packed, &nj->off_scales, ht.scales);
+    pack_table(&nj->packed, &nj->off_tiles, ht.tiles);
+    pack_table(&nj->packed, &nj->off_src_rows, ht.src_rows);
+    size_t o = align256(nj->packed.size());
+    nj->off_stats = o;
+    o = align256(o + 2 * sizeof(double));
+    nj->off_norm = o;
+    o = align256(o + 2 * sizeof(float));
+    nj->off_partials = o;
+    o = align256(o + (size_t)job.stats_blocks * 2 * sizeof(double));
+    nj->off_ds = o;
+    o = align256(o + (size_t)job.ds_total * 4 + 16);
+    nj->off_scr0 = o;
+    o = align256(o + (size_t)job.scr_cells * 4 + 16);
+    nj->off_scr1 = o;
+    o = align256(o + (size_t)job.scr_cells * 4 + 16);
+    if (round == 1 && o > kNoAllocBytes)
+      return fail(ctx, FFA_ERR_DEVICE, "ffa_search_noalloc: workspace layout overflow");
+  }
+  return FFA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -681,6 +861,10 @@ ffa_status ffa_create(int device, ffa_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
+  if (noalloc_setup(device, &c->na_ws) != hipSuccess) {
+    delete c;
+    return FFA_ERR_DEVICE;
+  }
   std::vector<uint32_t> ht;
   std::vector<uint16_t> rot;
   std::vector<int32_t> off;
@@ -782,6 +966,71 @@ ffa_status ffa_search(ffa_ctx* ctx, const void* series, int64_t nsamp,
   const int64_t zero = 0;
   return run_batch(ctx, 1, &series, &nsamp, params, &zero, snr_dev, capacity_rows, 0,
                    static_cast<hipStream_t>(stream));
+}
+
+ffa_status ffa_search_noalloc(ffa_ctx* ctx, const void* series, int64_t nsamp,
+                              const ffa_search_params* params, double* period_host,
+                              int32_t* bins_host, float* snr_dev, int64_t capacity_rows,
+                              void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !params || !snr_dev)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "null series, params or snr pointer");
+  if (!ctx->na_ws) return fail(ctx, FFA_ERR_DEVICE, "no static workspace on this device");
+  std::shared_ptr<SeriesPlan> plan;
+  ffa_status st = get_plan(ctx, *params, nsamp, &plan);
+  if (st != FFA_OK) return st;
+  if (capacity_rows < plan->rows)
+    return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
+  const int64_t zero = 0;
+  const Tiling na_tiling{ctx->tiling.lds_rows, ctx->tiling.levels_per_pass, 0, ctx->tiling.waves};
+  const std::string key = job_key(1, &series, &nsamp, params, &zero, na_tiling);
+  std::shared_ptr<NaJob> nj;
+  auto it = ctx->na_jobs.find(key);
+  if (it != ctx->na_jobs.end()) {
+    nj = it->second;
+  } else {
+    nj = std::make_shared<NaJob>();
+    st = build_na_job(ctx, series, nsamp, *params, plan, nj.get());
+    if (st != FFA_OK) return st;
+    if (ctx->na_jobs.size() >= 16) ctx->na_jobs.clear();
+    ctx->na_jobs[key] = nj;
+  }
+  if (period_host || bins_host) {
+    for (const Transform& t : plan->tr) {
+      const Octave& o = plan->oct[t.octave];
+      for (int32_t r = 0; r < t.keep; ++r) {
+        if (period_host) period_host[t.row0 + r] = trial_period(r, t.m, t.p, o.tau);
+        if (bins_host) bins_host[t.row0 + r] = t.p;
+      }
+    }
+  }
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  unsigned char* ws = static_cast<unsigned char*>(ctx->na_ws);
+  // the tables go after the status word; the copy is complete (and the host
+  // block free) before any kernel of this call is queued
+  HIP_TRY(ctx, hipMemcpyAsync(ws + kNoAllocHeader, nj->packed.data() + kNoAllocHeader,
+                              nj->packed.size() - kNoAllocHeader, hipMemcpyHostToDevice, hs),
+          "copy tables to the workspace");
+  HIP_TRY(ctx, hipStreamSynchronize(hs), "synchronise");
+  int32_t* flag = reinterpret_cast<int32_t*>(ws + kNoAllocFlagOffset);
+  HIP_TRY(ctx, launch_clear_flag(flag, hs), "clear status word");
+  ctx->na_used = true;
+  JobTables tb;
+  tb.series = reinterpret_cast<const SeriesDev*>(ws + nj->off_series);
+  tb.oct = reinterpret_cast<const OctaveDev*>(ws + nj->off_oct);
+  tb.xf = reinterpret_cast<const XformDesc*>(ws + nj->off_xf);
+  tb.scales = reinterpret_cast<const float*>(ws + nj->off_scales);
+  tb.tiles = reinterpret_cast<const TileDesc*>(ws + nj->off_tiles);
+  tb.src_rows = reinterpret_cast<const int32_t*>(ws + nj->off_src_rows);
+  Workspace w;
+  w.stats = reinterpret_cast<double*>(ws + nj->off_stats);
+  w.norm = reinterpret_cast<float*>(ws + nj->off_norm);
+  w.partials = reinterpret_cast<double*>(ws + nj->off_partials);
+  w.ds = ws + nj->off_ds;
+  w.scr0 = reinterpret_cast<float*>(ws + nj->off_scr0);
+  w.scr1 = reinterpret_cast<float*>(ws + nj->off_scr1);
+  w.flag = flag;
+  return enqueue_work(ctx, *nj->job, tb, w, snr_dev, hs, ctx->timing);
 }
 
 ffa_status ffa_search_ranges(ffa_ctx* ctx, const void* series, int64_t nsamp,
@@ -966,10 +1215,19 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream) {
   if (!ctx) return FFA_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
-  if (!ctx->flag.ptr) return FFA_OK;
   int32_t f = 0;
-  HIP_TRY(ctx, hipMemcpy(&f, ctx->flag.ptr, sizeof f, hipMemcpyDeviceToHost), "read flag");
-  HIP_TRY(ctx, launch_clear_flag(ctx->flag.as<int32_t>(), st), "clear flag");
+  if (ctx->flag.ptr) {
+    HIP_TRY(ctx, hipMemcpy(&f, ctx->flag.ptr, sizeof f, hipMemcpyDeviceToHost), "read flag");
+    HIP_TRY(ctx, launch_clear_flag(ctx->flag.as<int32_t>(), st), "clear flag");
+  }
+  if (ctx->na_used) {  // the status word of the no-allocation search
+    int32_t g = 0;
+    int32_t* na_flag = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(ctx->na_ws) +
+                                                  kNoAllocFlagOffset);
+    HIP_TRY(ctx, hipMemcpy(&g, na_flag, sizeof g, hipMemcpyDeviceToHost), "read flag");
+    HIP_TRY(ctx, launch_clear_flag(na_flag, st), "clear flag");
+    f |= g;
+  }
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
   if (f & 2) return fail(ctx, FFA_ERR_DEVICE, "a fold dependency wait timed out");
   if (f) return fail(ctx, FFA_ERR_DEGENERATE, "a normalised series had zero or non-finite variance");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/ffa.h"
 #include "ffa_internal.hpp"
 
 namespace ffa {
@@ -77,5 +78,16 @@ inline hipError_t set_lds_limit_once(const void* kernel, int bytes, bool* done) 
 
 // Sets a flag word to zero with a kernel (graph-capture friendly).
 hipError_t launch_clear_flag(int32_t* flag, hipStream_t stream);
+
+// Bytes of the static device workspace of ffa_search_noalloc (one per device),
+// and the offset in it of the status word (the first 256 bytes hold it; the
+// rest is laid out per call).
+constexpr size_t kNoAllocBytes = FFA_NOALLOC_WORKSPACE_BYTES;
+constexpr size_t kNoAllocFlagOffset = 0;
+constexpr size_t kNoAllocHeader = 256;
+
+// Device address of that workspace on `device`, which must be the current
+// device; looked up once per device and kept.
+hipError_t noalloc_setup(int device, void** ptr);
 
 }  // namespace ffa
