@@ -61,6 +61,10 @@ def parse():
                     help="autotune the tiling on --tune-series series first (the default tiling "
                          "is what the tuner picks for the batch workload)")
     ap.add_argument("--tune-series", type=int, default=16)
+    ap.add_argument("--waves", type=int, default=8,
+                    help="waves per workgroup of the first fold pass (8 or 16)")
+    ap.add_argument("--range-waves", type=int, default=0,
+                    help="waves per workgroup of the later fold passes (0: as --waves)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     return ap.parse_args()
@@ -406,12 +410,14 @@ def main():
         alg_ops = a.series * alg_ops_per_series(plan, len(cfg.widths))
         snr = torch.empty((rows1 * a.series, len(cfg.widths)), dtype=torch.float32,
                           device="cuda")
-        tiling = None
+        ffa.ffa_set_tiling(ctx, waves_per_group=a.waves, range_waves_per_group=a.range_waves)
+        tiling = {"waves_per_group": a.waves, "range_waves_per_group": a.range_waves}
         if a.autotune:
             k = min(a.tune_series, a.series)
             t = ffa.ffa_autotune(ctx, series[:k], prm[:k])
             tiling = {"waves_per_group": t.waves_per_group, "levels_per_pass": t.levels_per_pass,
-                      "persistent": t.persistent, "lds_rows": t.lds_rows}
+                      "persistent": t.persistent, "lds_rows": t.lds_rows,
+                      "range_waves_per_group": t.range_waves_per_group}
             log(f"variant {v}: autotuned on {k} series -> {tiling}")
         for _ in range(a.warmup):
             ffa.ffa_search_batch(ctx, series, prm, snr=snr)

@@ -213,21 +213,26 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);
  * all passes of a group of series in one persistent launch (tiles taken in
  * ticket order, later passes waiting on per-transform completion counters),
  * 0 launches one kernel per pass; waves_per_group: 16 (one workgroup per CU
- * with all 160 KiB of LDS) or 8 (two workgroups per CU, 80 KiB each). */
+ * with all 160 KiB of LDS) or 8 (two workgroups per CU, 80 KiB each);
+ * range_waves_per_group: the same for the passes after the first (range
+ * tiles), 0 = as waves_per_group (a persistent launch uses waves_per_group for
+ * every pass). */
 typedef struct {
   int32_t lds_rows;
   int32_t levels_per_pass;
   int32_t persistent;
   int32_t waves_per_group;
+  int32_t range_waves_per_group;
 } ffa_tiling;
 
 /* Reads or sets the context's tiling. */
 ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out);
 ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* tiling);
 
-/* Times candidate tilings (8 or 16 waves per workgroup, 3, 4 or 5 levels per
- * pass, per-pass or persistent launches, the largest tile that fits or tiles
- * of at most 40 rows) on a representative batch (same
+/* Times candidate tilings (8 or 16 waves per workgroup, the same or the other
+ * size for the range passes, 3, 4 or 5 levels per pass, per-pass or persistent
+ * launches, the largest tile that fits or tiles of at most 40 rows) on a
+ * representative batch (same
  * arguments as ffa_search_batch; outputs go to a context-owned buffer) with
  * HIP events on `stream`, keeps the fastest in the context and, if cache_path
  * is not NULL, appends it to that text file keyed by a hash of the batch's

@@ -58,7 +58,8 @@ class ffa_search_params(ctypes.Structure):
 
 class ffa_tiling(ctypes.Structure):
     _fields_ = [("lds_rows", ctypes.c_int32), ("levels_per_pass", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("range_waves_per_group", ctypes.c_int32)]
 
 
 class ffa_kernel_times(ctypes.Structure):
@@ -350,8 +351,10 @@ def ffa_get_tiling(ctx) -> ffa_tiling:
 
 
 def ffa_set_tiling(ctx, lds_rows: int = 0, levels_per_pass: int = 5,
-                   persistent: bool = False, waves_per_group: int = 8) -> None:
-    t = ffa_tiling(lds_rows, levels_per_pass, 1 if persistent else 0, waves_per_group)
+                   persistent: bool = False, waves_per_group: int = 8,
+                   range_waves_per_group: int = 0) -> None:
+    t = ffa_tiling(lds_rows, levels_per_pass, 1 if persistent else 0, waves_per_group,
+                   range_waves_per_group)
     _check(lib().ffa_set_tiling(ctx, ctypes.byref(t)), ctx)
 
 

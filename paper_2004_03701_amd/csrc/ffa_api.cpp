@@ -370,14 +370,16 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   std::vector<int32_t>& need = ht->need;
   job->scr_cells = 0;
   job->persistent = tiling.persistent != 0;
+  if (job->persistent) job->tiling.range_waves = 0;  // one launch: one workgroup size
   for (const GroupSpan& g : spans) {
     Group grp;
     if (!job->persistent) {
       std::vector<std::vector<TileDesc>> passes;
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
-        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, tiling),
-                                  tiling.levels_per_pass, false, &passes))
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, job->tiling),
+                                  range_rows_capacity(x.p, job->tiling),
+                                  job->tiling.levels_per_pass, false, &passes))
           return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
       }
       for (auto& ps : passes) {
@@ -398,8 +400,9 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       for (size_t k = g.xf0; k < g.xf1; ++k) {
         const XformDesc& x = xf[k];
         std::vector<std::vector<TileDesc>> passes;
-        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, tiling),
-                                  tiling.levels_per_pass, false, &passes))
+        if (!plan_transform_tiles((int32_t)k, x.m, x.p, x.keep, rows_capacity(x.p, job->tiling),
+                                  range_rows_capacity(x.p, job->tiling),
+                                  job->tiling.levels_per_pass, false, &passes))
           return fail(ctx, FFA_ERR_INVALID_ARG, "a transform's tiles do not fit the tile rows");
         const int64_t local = (int64_t)(k - g.xf0);
         const int32_t cbase = (int32_t)(local * kMaxPasses);
@@ -597,6 +600,7 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
       pa.ntiles = l.ntiles;
       // a first pass holds full tiles only, a later pass range tiles only
       pa.pairs_only = pairs ? (k == 0 ? 2 : 3) : 0;
+      pa.waves = k == 0 ? job.tiling.waves : job.tiling.waves_of_range();
       TimedScope ts(ctx, 2, stream, timed);
       HIP_TRY(ctx, launch_pass(pa, stream), "fold pass kernel");
     }
@@ -616,7 +620,7 @@ std::string job_key(int32_t nseries, const void* const* series, const int64_t* n
                     const Tiling& tiling) {
   std::ostringstream k;
   k << nseries << '|' << tiling.lds_rows << ',' << tiling.levels_per_pass << ','
-    << tiling.persistent << ',' << tiling.waves << '|';
+    << tiling.persistent << ',' << tiling.waves << ',' << tiling.range_waves << '|';
   for (int i = 0; i < nseries; ++i)
     k << series[i] << ',' << row_offset[i] << ',' << params[i].normalise << ','
       << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
@@ -982,7 +986,8 @@ ffa_status ffa_search_noalloc(ffa_ctx* ctx, const void* series, int64_t nsamp,
   if (capacity_rows < plan->rows)
     return fail(ctx, FFA_ERR_BUFFER_TOO_SMALL, "snr buffer too small for the periodogram rows");
   const int64_t zero = 0;
-  const Tiling na_tiling{ctx->tiling.lds_rows, ctx->tiling.levels_per_pass, 0, ctx->tiling.waves};
+  const Tiling na_tiling{ctx->tiling.lds_rows, ctx->tiling.levels_per_pass, 0, ctx->tiling.waves,
+                         ctx->tiling.range_waves};
   const std::string key = job_key(1, &series, &nsamp, params, &zero, na_tiling);
   std::shared_ptr<NaJob> nj;
   auto it = ctx->na_jobs.find(key);
@@ -1106,7 +1111,8 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
     return FFA_OK;
   }
   if (!plan_transform_tiles(0, m, p, m, rows_capacity(p, ctx->tiling),
-                            ctx->tiling.levels_per_pass, true, &passes))
+                            range_rows_capacity(p, ctx->tiling), ctx->tiling.levels_per_pass, true,
+                            &passes))
     return fail(ctx, FFA_ERR_INVALID_ARG, "the transform's tiles do not fit the tile rows");
   std::vector<TileDesc> tiles;
   std::vector<Launch> launches;
@@ -1147,6 +1153,7 @@ ffa_status ffa_transform(ffa_ctx* ctx, const float* in, int32_t m, int32_t p, fl
     pa.tiles = job->tiles.as<TileDesc>() + l.tile_off;
     pa.ntiles = l.ntiles;
     pa.pairs_only = pairs ? (k == 0 ? 2 : 3) : 0;
+    pa.waves = k == 0 ? ctx->tiling.waves : ctx->tiling.waves_of_range();
     HIP_TRY(ctx, launch_pass(pa, st), "fold pass kernel");
   }
   // keep the tables alive until the work is done
@@ -1240,6 +1247,7 @@ ffa_status ffa_get_tiling(const ffa_ctx* ctx, ffa_tiling* out) {
   out->levels_per_pass = ctx->tiling.levels_per_pass;
   out->persistent = ctx->tiling.persistent;
   out->waves_per_group = ctx->tiling.waves;
+  out->range_waves_per_group = ctx->tiling.range_waves;
   return FFA_OK;
 }
 
@@ -1247,14 +1255,17 @@ ffa_status ffa_set_tiling(ffa_ctx* ctx, const ffa_tiling* t) {
   if (!ctx || !t) return FFA_ERR_INVALID_ARG;
   if (t->lds_rows < 0 || (t->lds_rows > 0 && t->lds_rows < 16) || t->levels_per_pass < 1 ||
       t->levels_per_pass > kMaxRangeLevels || (t->persistent != 0 && t->persistent != 1) ||
-      (t->waves_per_group != kWavesLarge && t->waves_per_group != kWavesSmall))
+      (t->waves_per_group != kWavesLarge && t->waves_per_group != kWavesSmall) ||
+      (t->range_waves_per_group != 0 && t->range_waves_per_group != kWavesLarge &&
+       t->range_waves_per_group != kWavesSmall))
     return fail(ctx, FFA_ERR_INVALID_ARG,
                 "need lds_rows = 0 or >= 16, 1 <= levels_per_pass <= 5, persistent 0 or 1, "
-                "waves_per_group 8 or 16");
+                "waves_per_group 8 or 16, range_waves_per_group 0, 8 or 16");
   ctx->tiling.lds_rows = t->lds_rows;
   ctx->tiling.levels_per_pass = t->levels_per_pass;
   ctx->tiling.persistent = t->persistent;
   ctx->tiling.waves = t->waves_per_group;
+  ctx->tiling.range_waves = t->range_waves_per_group;
   return FFA_OK;
 }
 
@@ -1323,20 +1334,22 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
       best->levels_per_pass = t.levels_per_pass;
       best->persistent = t.persistent;
       best->waves_per_group = t.waves;
+      best->range_waves_per_group = t.range_waves;
     }
   };
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char key[64];
-      int lr, lv, pe, wv;
+      int lr, lv, pe, wv, rw;
       bool hit = false;
       Tiling t;
-      while (fscanf(f, "%63s %d %d %d %d", key, &lr, &lv, &pe, &wv) == 5) {
+      while (fscanf(f, "%63s %d %d %d %d %d", key, &lr, &lv, &pe, &wv, &rw) == 6) {
         if (shape == key) {
           t.lds_rows = lr;
           t.levels_per_pass = lv;
           t.persistent = pe;
           t.waves = wv;
+          t.range_waves = rw;
           hit = true;
         }
       }
@@ -1369,11 +1382,14 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
   const bool timing = ctx->timing;
   ctx->timing = false;
   for (int waves : {kWavesSmall, kWavesLarge})
+    for (int range_waves : {0, kWavesSmall + kWavesLarge - waves})
     for (int levels : {3, 4, 5})
       for (int persistent : {0, 1})
       for (int lds_rows : {0, kTuneSmallTileRows}) {
+        if (persistent && range_waves) continue;  // one launch: one workgroup size
         Tiling t;
         t.waves = waves;
+        t.range_waves = range_waves;
         t.levels_per_pass = levels;
         t.persistent = persistent;
         t.lds_rows = lds_rows;
@@ -1410,8 +1426,8 @@ ffa_status ffa_autotune(ffa_ctx* ctx, int32_t nseries, const void* const* series
   report(winner);
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
-      fprintf(f, "%s %d %d %d %d\n", shape.c_str(), winner.lds_rows, winner.levels_per_pass,
-              winner.persistent, winner.waves);
+      fprintf(f, "%s %d %d %d %d %d\n", shape.c_str(), winner.lds_rows, winner.levels_per_pass,
+              winner.persistent, winner.waves, winner.range_waves);
       fclose(f);
     }
   }

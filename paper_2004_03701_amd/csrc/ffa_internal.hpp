@@ -39,8 +39,12 @@ constexpr int kMetaInts = 6 * kMetaNodes + kMaxRangeLevels + 4;
 // LDS of a CU (gfx950: 160 KiB); a workgroup of w waves uses w / 16 of it.
 constexpr int kLdsBytes = 160 * 1024;
 inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWavesLarge * waves; }
-// LDS set aside for the S/N step.
+// LDS set aside for the S/N step; range tiles keep their pair-operation
+// records of kOpInts ints here during the merges, so a range tile has at most
+// kMaxTileOps operations.
 constexpr int kSnrLdsBytes = 10 * 1024;
+constexpr int kOpInts = 6;
+constexpr int kMaxTileOps = kSnrLdsBytes / (kOpInts * 4);
 
 // Bins past p that a row in LDS keeps as a copy of bins 0 .. kHalo - 1, so a
 // rotated read of kChunk + 1 consecutive bins (the two rows of a merge pair)

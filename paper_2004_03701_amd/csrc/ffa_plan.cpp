@@ -151,6 +151,10 @@ int32_t rows_capacity(int32_t p, const Tiling& t) {
   return ffa::rows_capacity(p, t.lds_rows, t.waves);
 }
 
+int32_t range_rows_capacity(int32_t p, const Tiling& t) {
+  return ffa::rows_capacity(p, t.lds_rows, t.waves_of_range());
+}
+
 void node_geometry(int64_t m, int d, int64_t node, int64_t* r0, int64_t* n) {
   int64_t base = 0, size = m;
   for (int b = d - 1; b >= 0; --b) {
@@ -271,6 +275,40 @@ int64_t range_peak_rows(int64_t n, int64_t lo, int64_t hi, int levels) {
   return mx;
 }
 
+// Pair operations that make rows [lo, hi) of an n-row node: rows s and s + 1
+// share their tail row when s has the parity of n, so a leading row of the
+// other parity and a trailing unpaired row are singles; a one-row block is
+// one copy.
+int64_t node_pair_ops(int64_t n, int64_t lo, int64_t hi) {
+  if (hi <= lo || n <= 0) return 0;
+  if (n == 1) return 1;
+  const int64_t lead = ((lo & 1) != (n & 1)) ? 1 : 0;
+  const int64_t rem = hi - lo - lead;
+  return lead + (rem >> 1) + (rem & 1);
+}
+
+// Pair operations of every merge level of a range tile (rows [lo, hi) of an
+// n-row node from the rows `levels` levels below).
+int64_t range_ops(int64_t n, int64_t lo, int64_t hi, int levels) {
+  if (levels == 0 || hi <= lo) return 0;
+  int64_t ops = node_pair_ops(n, lo, hi);
+  if (n <= 1) {
+    if (n == 1) ops += range_ops(1, 0, 1, levels - 1);
+    return ops;
+  }
+  int64_t mh = n / 2, mt = n - mh, i0, j0, i1, j1;
+  merge_indices(n, lo, &i0, &j0);
+  merge_indices(n, hi - 1, &i1, &j1);
+  return ops + range_ops(mh, i0, i1 + 1, levels - 1) + range_ops(mt, j0, j1 + 1, levels - 1);
+}
+
+// Whether a range tile's rows fit the tile at every level and its pair
+// operations fit the record area.
+bool range_fits(int64_t n, int64_t lo, int64_t hi, int levels, int64_t rows_cap) {
+  return range_peak_rows(n, lo, hi, levels) <= rows_cap &&
+         range_ops(n, lo, hi, levels) <= kMaxTileOps;
+}
+
 }  // namespace
 
 namespace {
@@ -349,10 +387,10 @@ void attach_source_rows(std::vector<TileDesc>* tiles, const XformDesc* xf,
 }
 
 bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
-                          int32_t levels_per_pass, bool out_rows,
+                          int32_t range_rows_cap, int32_t levels_per_pass, bool out_rows,
                           std::vector<std::vector<TileDesc>>* passes) {
   (void)p;
-  if (rows_cap < 2) return false;
+  if (rows_cap < 2 || range_rows_cap < 2) return false;
   auto pass = [&](size_t k) -> std::vector<TileDesc>& {
     if (passes->size() <= k) passes->resize(k + 1);
     return (*passes)[k];
@@ -376,7 +414,7 @@ bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
   // one output row of an L-level range tile reads up to 2^L rows at the
   // bottom level, so the levels of a pass are capped where 2^L <= rows_cap
   int L = std::max(1, std::min<int>(levels_per_pass, kMaxRangeLevels));
-  while (L > 1 && (1 << L) > rows_cap) --L;
+  while (L > 1 && (1 << L) > range_rows_cap) --L;
   const int npu = (db + L - 1) / L;
   int d_src = db;
   for (int k = 0; k < npu; ++k) {
@@ -390,12 +428,12 @@ bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_
       const int64_t end = last ? keep : n;
       int64_t s0 = 0;
       while (s0 < end) {
-        if (range_peak_rows(n, s0, s0 + 1, lv) > rows_cap) return false;
+        if (!range_fits(n, s0, s0 + 1, lv, range_rows_cap)) return false;
         // largest s1 whose rows fit at every level of the pass
         int64_t lo = s0 + 1, hi = end;
         while (lo < hi) {
           int64_t mid = (lo + hi + 1) / 2;
-          if (range_peak_rows(n, s0, mid, lv) <= rows_cap)
+          if (range_fits(n, s0, mid, lv, range_rows_cap))
             lo = mid;
           else
             hi = mid - 1;

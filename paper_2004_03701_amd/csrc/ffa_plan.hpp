@@ -54,17 +54,22 @@ struct Tiling {
   int32_t levels_per_pass = 5;  // 1..kMaxRangeLevels
   int32_t persistent = 0;       // 1: one persistent launch per group of series
   int32_t waves = kWavesSmall;  // waves per workgroup: 16 (one per CU) or 8 (two per CU)
+  int32_t range_waves = 0;      // the same for the range passes (0: as `waves`)
+  int32_t waves_of_range() const { return range_waves > 0 ? range_waves : waves; }
 };
 
-// Rows of a p-bin profile tile that fit in one workgroup's LDS.
+// Rows of a p-bin profile tile that fit in one workgroup's LDS: full tiles
+// (first passes) and range tiles (later passes).
 int32_t rows_capacity(int32_t p, const Tiling& t);
+int32_t range_rows_capacity(int32_t p, const Tiling& t);
 
 // Tiles of one transform, grouped by pass. `xf` is the transform's index in
-// the launch's transform table. Appends to passes[k] for pass k. The levels of
-// a range pass are capped so that every tile's rows fit rows_cap at every
-// level; returns false (and the plan must not be used) if some tile would not.
+// the launch's transform table. Appends to passes[k] for pass k. Full tiles
+// hold at most rows_cap rows; the levels of a range pass are capped so that
+// every range tile's rows fit range_rows_cap at every level; returns false (and
+// the plan must not be used) if some tile would not.
 bool plan_transform_tiles(int32_t xf, int32_t m, int32_t p, int32_t keep, int32_t rows_cap,
-                          int32_t levels_per_pass, bool out_rows,
+                          int32_t range_rows_cap, int32_t levels_per_pass, bool out_rows,
                           std::vector<std::vector<TileDesc>>* passes);
 
 // Merge schedules of full subtrees of 2..kMaxFullRows rows (PassArgs).

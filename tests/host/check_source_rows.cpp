@@ -8,7 +8,8 @@
 // 2. Every tile the planner emits fits the workgroup's LDS: over a grid of
 //    (m, p, tiling), a full tile holds at most rows_capacity rows, and a range
 //    tile keeps at most rows_capacity rows at every level of its subtree and
-//    at most kSnrLdsBytes of pair operations (six ints each).
+//    at most kSnrLdsBytes of pair-operation records (kOpInts ints each).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -119,25 +120,30 @@ static int check_lists() {
   return 0;
 }
 
+constexpr int kOpBytes = kOpInts * 4;
+
 static int check_plan_fits() {
+  int max_range_ops = 0;
   std::vector<std::pair<int, int>> shapes = {
       {200, 1280}, {500, 600}, {497, 519}, {1000, 1000}, {300, 1280}, {500, 1000}, {1073, 259},
       {1500, 61},  {12000, 33}, {2048, 128}, {42406, 259}, {4000, 700}, {900, 1100}, {3, 1280}};
   std::mt19937 g(11);
-  for (int q = 0; q < 120; ++q) shapes.push_back({2 + (int)(g() % 20000), 2 + (int)(g() % 1279)});
+  for (int q = 0; q < 60; ++q) shapes.push_back({2 + (int)(g() % 20000), 2 + (int)(g() % 1279)});
   long tiles = 0;
   for (auto [m, p] : shapes) {
     for (int waves : {kWavesSmall, kWavesLarge})
+      for (int range_waves : {0, kWavesSmall + kWavesLarge - waves})
       for (int lds_rows : {0, 16, 24, 40})
         for (int levels = 1; levels <= kMaxRangeLevels; ++levels) {
           if ((int64_t)m * p > (int64_t(1) << 31)) continue;
           Tiling t;
           t.waves = waves;
+          t.range_waves = range_waves;
           t.lds_rows = lds_rows;
           t.levels_per_pass = levels;
-          const int R = rows_capacity(p, t);
+          const int R = rows_capacity(p, t), Rr = range_rows_capacity(p, t);
           std::vector<std::vector<TileDesc>> passes;
-          if (!plan_transform_tiles(0, m, p, m, R, levels, false, &passes)) {
+          if (!plan_transform_tiles(0, m, p, m, R, Rr, levels, false, &passes)) {
             printf("plan refused m=%d p=%d R=%d levels=%d\n", m, p, R, levels);
             return 1;
           }
@@ -162,20 +168,22 @@ static int check_plan_fits() {
                   rows += M.hi[h] - M.lo[h];
                   if (l < tl.levels) ops += pair_ops(M.n[h], M.lo[h], M.hi[h]);
                 }
-                if (rows > R) {
-                  printf("range tile keeps %d rows > %d at level %d (m=%d p=%d L=%d)\n", rows, R,
+                if (rows > Rr) {
+                  printf("range tile keeps %d rows > %d at level %d (m=%d p=%d L=%d)\n", rows, Rr,
                          l, m, p, tl.levels);
                   return 1;
                 }
               }
-              if (ops * 6 * 4 > kSnrLdsBytes) {
+              max_range_ops = std::max(max_range_ops, ops);
+              if (ops * kOpBytes > kSnrLdsBytes) {
                 printf("range tile has %d pair operations (m=%d p=%d)\n", ops, m, p);
                 return 1;
               }
             }
         }
   }
-  printf("ok: %ld planned tiles fit\n", tiles);
+  printf("ok: %ld planned tiles fit (most pair operations of a range tile %d, room for %d)\n",
+         tiles, max_range_ops, kSnrLdsBytes / kOpBytes);
   return 0;
 }
 
