@@ -452,7 +452,7 @@ def main():
         ffa.ffa_set_tiling(ctx)
         ms = 1e3 * wall / a.steps
         profiles = rows1 * a.series
-        esize = 4  # the folded (downsampled) series are FP32 for every storage type
+        esize = 4 if tdt is None else 2  # the folded (downsampled) series: the storage type
         alg_bytes = a.series * (int(bins.sum()) * esize + rows1 * len(cfg.widths) * 4)
         fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
         res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),

@@ -42,8 +42,9 @@ typedef enum {
   FFA_ERR_NOT_IMPLEMENTED = -7
 } ffa_status;
 
-/* Storage type of an input series. Arithmetic is FP32 (FP64 for the
- * normalisation statistics and the S/N noise constants) whatever the storage. */
+/* Storage type of an input series (and of its downsampled series). Arithmetic
+ * is FP32 (FP64 for the normalisation statistics and the S/N noise constants)
+ * whatever the storage. */
 typedef enum { FFA_F32 = 0, FFA_BF16 = 1, FFA_F16 = 2 } ffa_dtype;
 
 typedef struct ffa_ctx ffa_ctx;
@@ -64,8 +65,12 @@ typedef struct ffa_ctx ffa_ctx;
  *                device (Sec. 5.2); 0: the series is used as given (it should
  *                then have zero mean and unit variance).
  *   dtype        ffa_dtype of the series. The statistics and the
- *                downsampler read it in this type; the downsampled series
- *                and everything after it are FP32. */
+ *                downsampler read it in this type, and the downsampled
+ *                series are stored in it too (a BF16 or FP16 search reads
+ *                half the bytes of an FP32 one); the fold converts them on
+ *                load, and every sum from there on is FP32. With FP16 storage
+ *                the downsampled samples must fit FP16 (as they do for a
+ *                normalised series). */
 typedef struct {
   double tsamp;
   double period_min;

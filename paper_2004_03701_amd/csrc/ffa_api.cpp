@@ -483,7 +483,7 @@ Workspace ctx_workspace(ffa_ctx* ctx) {
 // Grows the context workspace for a job. Captured graphs hold the old
 // addresses, so they are dropped whenever a buffer moves.
 ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
-  const size_t db = 4;  // downsampled series: FP32 whatever the input's storage
+  const size_t db = job.dtype == FFA_F32 ? 4 : 2;  // downsampled series: the input's type
   DevBuf* bufs[] = {&ctx->ds_buf, &ctx->scr0, &ctx->scr1, &ctx->stats, &ctx->norm,
                     &ctx->partials, &ctx->flag, &ctx->counters, &ctx->ticket};
   const size_t want[] = {(size_t)job.ds_total * db + 16,
@@ -555,7 +555,9 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
   }
   {
   TimedScope ts(ctx, 1, stream, timed);
-  HIP_TRY(ctx, launch_downsample(sd, job.nseries, tb.oct, ws.norm, job.dtype, ws.ds, FFA_F32,
+  // the downsampled series are stored in the input's type (BF16 and FP16
+  // storage halve the fold's input reads); the fold converts them on load
+  HIP_TRY(ctx, launch_downsample(sd, job.nseries, tb.oct, ws.norm, job.dtype, ws.ds, job.dtype,
                                  job.ds_blocks, job.ds_lds_floats, stream),
           "downsample kernel");
   }
@@ -564,7 +566,7 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
   pa.waves = job.tiling.waves;
   pa.xf = tb.xf;
   pa.in = ws.ds;
-  pa.in_dtype = FFA_F32;
+  pa.in_dtype = job.dtype;
   pa.num_widths = job.num_widths;
   pa.scr0 = ws.scr0;
   pa.scr1 = ws.scr1;
@@ -838,7 +840,7 @@ ffa_status build_na_job(ffa_ctx* ctx, const void* series, int64_t nsamp,
     nj->off_partials = o;
     o = align256(o + (size_t)job.stats_blocks * 2 * sizeof(double));
     nj->off_ds = o;
-    o = align256(o + (size_t)job.ds_total * 4 + 16);
+    o = align256(o + (size_t)job.ds_total * (job.dtype == FFA_F32 ? 4 : 2) + 16);
     nj->off_scr0 = o;
     o = align256(o + (size_t)job.scr_cells * 4 + 16);
     nj->off_scr1 = o;

@@ -1951,15 +1951,18 @@ template <bool kPersist>
 hipError_t dispatch(const PassArgs& args, int grid, hipStream_t stream) {
   const bool j1 = col_iters(args.max_p) == 1;
   const bool big = args.waves == kWavesLarge;
+// The folded (downsampled) series are stored in the input's type. Range
+// tiles read only the FP32 scratch rows, so the range-tile kernel is compiled
+// once.
 #define FFA_LAUNCH(WV, JS, DT)                                                        \
   (kPersist ? launch_persist_t<WV, JS, DT>(args, grid, stream)                        \
    : (JS == 1 && args.pairs_only == 2) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 2 : 0)>(args, stream) \
-   : (JS == 1 && args.pairs_only == 3) ? launch_pass_t<WV, JS, DT, (JS == 1 ? 3 : 0)>(args, stream) \
+   : (JS == 1 && args.pairs_only == 3) ? launch_pass_t<WV, JS, FFA_F32, (JS == 1 ? 3 : 0)>(args, stream) \
                                        : launch_pass_t<WV, JS, DT, 0>(args, stream))
-// the folded series are FP32 (the downsampler writes FP32 whatever the
-// input's storage type)
-#define FFA_BY_DT(WV, JS) \
-  (args.in_dtype == FFA_F32 ? FFA_LAUNCH(WV, JS, FFA_F32) : hipErrorInvalidValue)
+#define FFA_BY_DT(WV, JS)                                                  \
+  (args.in_dtype == FFA_F32    ? FFA_LAUNCH(WV, JS, FFA_F32)              \
+   : args.in_dtype == FFA_BF16 ? FFA_LAUNCH(WV, JS, FFA_BF16)             \
+   : args.in_dtype == FFA_F16  ? FFA_LAUNCH(WV, JS, FFA_F16) : hipErrorInvalidValue)
   if (big) return j1 ? FFA_BY_DT(kWavesLarge, 1) : FFA_BY_DT(kWavesLarge, 0);
   return j1 ? FFA_BY_DT(kWavesSmall, 1) : FFA_BY_DT(kWavesSmall, 0);
 #undef FFA_BY_DT
