@@ -7,7 +7,8 @@ plan, downsampler, folding transforms and S/N, written from the paper.
 
 Layout:
   * ``ffa_oracle.c`` -- the heavy loops in plain C, double precision
-    (path offsets, brute-force fold, depth-first FFA, downsampling, boxcar S/N);
+    (path offsets, brute-force fold, depth-first FFA, downsampling, boxcar S/N,
+    running median);
   * this module -- the period plan and normalisation (numpy FP64 / Python
     integers) and the ctypes glue.
 
@@ -27,7 +28,10 @@ Readings of the paper used here, where it is silent or ambiguous:
   * the noise variance of a downsampled sample is ds for an integer factor and
     ds - 1/3 otherwise (Sec. 5.3, App. A.4);
   * normalisation uses the population standard deviation of the whole raw
-    series (Sec. 5.2).
+    series (Sec. 5.2);
+  * de-reddening (Sec. 5.2) subtracts the running median over an odd window
+    centred on each sample, cut at the ends of the series, the median of an
+    even count (only at the ends) being the lower of the two middle values.
 """
 from __future__ import annotations
 
@@ -83,6 +87,8 @@ def _load():
     lib.oracle_transforms_snr.argtypes = [pd, i64, pi64, pi64, pi64, pd, pi64, pi64, i32, pi32,
                                           i32, pd]
     lib.oracle_transforms_snr.restype = ctypes.c_int
+    lib.oracle_running_median.argtypes = [pd, i64, i64, pd, pd]
+    lib.oracle_running_median.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -137,6 +143,22 @@ def downsample(x: np.ndarray, ds_fx: int, nout: int) -> np.ndarray:
     _load().oracle_downsample(_p(x, ctypes.c_double), x.size, ds_fx, nout,
                               _p(y, ctypes.c_double))
     return y
+
+
+def running_median(x: np.ndarray, window: int):
+    """De-reddening by a running median (Sec. 5.2): returns (y, med) with
+    med[i] the median of the `window` (odd) samples centred on i, the window
+    cut at the ends of the series (the median of n samples being the
+    ((n - 1) // 2)-th smallest, 0-based), and y = x - med, in FP64."""
+    if window < 1 or window % 2 == 0:
+        raise ValueError("window must be odd and positive")
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    med = np.empty_like(x)
+    y = np.empty_like(x)
+    if _load().oracle_running_median(_p(x, ctypes.c_double), x.size, window,
+                                     _p(med, ctypes.c_double), _p(y, ctypes.c_double)) != 0:
+        raise MemoryError("oracle_running_median")
+    return y, med
 
 
 def normalise_stats(x: np.ndarray):

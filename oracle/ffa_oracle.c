@@ -212,3 +212,78 @@ int oracle_transforms_snr(const double* y, int64_t ntr, const int64_t* y_off, co
   }
   return err ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------
+ * De-reddening by a running median (Sec. 5.2). Output i is x[i] minus the
+ * median of the samples in the window of `window` (odd) samples centred on
+ * i, the window cut at the ends of the series; the median of n samples is
+ * their k-th smallest value, k = (n - 1) / 2 (0-based; for even n, at the
+ * ends, the lower of the two middle values). The k-th smallest is found by
+ * the textbook order-statistic method: every sample gets its rank in the
+ * sort of the whole series by (value, index); a Fenwick tree counts the
+ * ranks present in the window; the k-th present rank is found by descending
+ * the tree.
+ * ------------------------------------------------------------------------ */
+
+static const double* g_sort_x;
+
+static int cmp_value_index(const void* a, const void* b) {
+  const int64_t i = *(const int64_t*)a, j = *(const int64_t*)b;
+  const double xi = g_sort_x[i], xj = g_sort_x[j];
+  if (xi < xj) return -1;
+  if (xi > xj) return 1;
+  return (i > j) - (i < j);
+}
+
+static void bit_add(int32_t* tree, int64_t n, int64_t pos, int32_t d) {
+  for (int64_t q = pos + 1; q <= n; q += q & (-q)) tree[q] += d;
+}
+
+/* Smallest 0-based position whose prefix count reaches k + 1. */
+static int64_t bit_kth(const int32_t* tree, int64_t n, int64_t k) {
+  int64_t pos = 0, step = 1;
+  while (step * 2 <= n) step *= 2;
+  int64_t rem = k + 1;
+  for (; step > 0; step /= 2) {
+    if (pos + step <= n && tree[pos + step] < rem) {
+      pos += step;
+      rem -= tree[pos];
+    }
+  }
+  return pos;  /* 1-based position pos + 1, i.e. 0-based pos */
+}
+
+/* med[i] = median of the window of output i; y[i] = x[i] - med[i]. Returns
+ * 0, or -1 on allocation failure. */
+int oracle_running_median(const double* x, int64_t n, int64_t window, double* med, double* y) {
+  if (n <= 0) return 0;
+  const int64_t h = window / 2;
+  int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* rank = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int32_t* tree = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!order || !rank || !tree) {
+    free(order);
+    free(rank);
+    free(tree);
+    return -1;
+  }
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  g_sort_x = x;
+  qsort(order, (size_t)n, sizeof(int64_t), cmp_value_index);
+  for (int64_t r = 0; r < n; ++r) rank[order[r]] = r;
+  int64_t s = 0, e = 0; /* samples [s, e) are in the tree */
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t ws = i - h < 0 ? 0 : i - h;
+    const int64_t we = i + h + 1 > n ? n : i + h + 1;
+    while (e < we) bit_add(tree, n, rank[e++], 1);
+    while (s < ws) bit_add(tree, n, rank[s++], -1);
+    const int64_t cnt = we - ws;
+    const int64_t r = bit_kth(tree, n, (cnt - 1) / 2);
+    med[i] = x[order[r]];
+    y[i] = x[i] - med[i];
+  }
+  free(order);
+  free(rank);
+  free(tree);
+  return 0;
+}
