@@ -208,6 +208,20 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
                           const double* stats_dev, uint64_t ds_fx, int64_t nout, void* out_dev,
                           void* stream);
 
+/* De-reddening by a running median (Sec. 5.2): the low-frequency noise
+ * subtracted before the series is normalised and searched. out[i] =
+ * series[i] - the median of the `window` samples centred on i (window odd,
+ * >= 1), the window cut at the ends of the series; the median of n samples
+ * is their ((n - 1) / 2)-th smallest value, 0-based (the lower middle value
+ * for an even count, which only occurs at the ends). The filter leaves any
+ * constant impulse narrower than half the window intact. series: DEVICE,
+ * nsamp samples of `dtype`; out_dev: DEVICE, nsamp samples of `out_dtype`
+ * (may not alias series). The median is one of the samples, so with FP32
+ * output the result is the exact difference rounded once. Non-finite
+ * samples give unspecified medians. Asynchronous on `stream`. */
+ffa_status ffa_running_median(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                              int32_t window, void* out_dev, int32_t out_dtype, void* stream);
+
 /* Waits for the stream and reports FFA_ERR_DEGENERATE if a series normalised
  * since the previous call to ffa_sync_status had zero or non-finite variance. */
 ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream);

@@ -36,7 +36,7 @@ EXPORTED = (
     "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
     "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
     "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch", "ffa_search_ranges",
-    "ffa_search_noalloc",
+    "ffa_search_noalloc", "ffa_running_median",
 )
 
 FFA_NOALLOC_WORKSPACE_BYTES = 128 << 20
@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
         "ffa_plan_export": ([pp, i64, vp, vp, vp, vp, vp, vp, i64], i32),
         "ffa_search": ([vp, vp, i64, pp, vp, vp, vp, i64, vp], i32),
         "ffa_search_noalloc": ([vp, vp, i64, pp, vp, vp, vp, i64, vp], i32),
+        "ffa_running_median": ([vp, vp, i64, i32, i32, vp, i32, vp], i32),
         "ffa_search_batch": ([vp, i32, P(vp), P(i64), pp, P(i64), vp, i64, i32, vp], i32),
         "ffa_transform": ([vp, vp, i32, i32, vp, vp], i32),
         "ffa_series_stats": ([vp, vp, i64, i32, vp, vp], i32),
@@ -259,6 +260,20 @@ def ffa_search_noalloc(ctx, series, params: ffa_search_params, snr, stream=None,
                                   snr.data_ptr(), snr.shape[0], _stream(stream))
     _check(st, ctx)
     return per, bins, snr
+
+
+def ffa_running_median(ctx, series, window: int, out=None, out_dtype: int = FFA_F32,
+                       stream=None):
+    """De-reddened copy of a device series (torch tensor of float32, bfloat16
+    or float16): series minus its running median over `window` samples."""
+    import torch
+    dt = {torch.float32: FFA_F32, torch.bfloat16: FFA_BF16, torch.float16: FFA_F16}[series.dtype]
+    tdt = {FFA_F32: torch.float32, FFA_BF16: torch.bfloat16, FFA_F16: torch.float16}[out_dtype]
+    if out is None:
+        out = torch.empty(series.numel(), dtype=tdt, device=series.device)
+    _check(lib().ffa_running_median(ctx, series.data_ptr(), series.numel(), dt, window,
+                                    out.data_ptr(), out_dtype, _stream(stream)), ctx)
+    return out
 
 
 def ffa_search_batch(ctx, series: Sequence, params: Sequence[ffa_search_params], snr=None,

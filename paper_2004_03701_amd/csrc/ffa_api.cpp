@@ -1220,6 +1220,25 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   return FFA_OK;
 }
 
+ffa_status ffa_running_median(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
+                              int32_t window, void* out_dev, int32_t out_dtype, void* stream) {
+  if (!ctx) return FFA_ERR_INVALID_ARG;
+  if (!series || !out_dev) return fail(ctx, FFA_ERR_INVALID_ARG, "null series or out");
+  if (nsamp < 1 || nsamp > INT32_MAX) return fail(ctx, FFA_ERR_INVALID_ARG, "nsamp out of range");
+  if (dtype != FFA_F32 && dtype != FFA_BF16 && dtype != FFA_F16)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "unknown dtype");
+  if (out_dtype != FFA_F32 && out_dtype != FFA_BF16 && out_dtype != FFA_F16)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "unknown out_dtype");
+  if (window < 1 || window % 2 == 0)
+    return fail(ctx, FFA_ERR_INVALID_ARG, "the median window must be odd and positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(ctx, grow(ctx, ctx->flag, 16, true), "allocate status word");
+  HIP_TRY(ctx, launch_running_median(series, nsamp, dtype, window, out_dev, out_dtype,
+                                     ctx->flag.as<int32_t>(), st),
+          "running median kernel");
+  return FFA_OK;
+}
+
 ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream) {
   if (!ctx) return FFA_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1239,6 +1258,7 @@ ffa_status ffa_sync_status(ffa_ctx* ctx, void* stream) {
   }
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");
   if (f & 2) return fail(ctx, FFA_ERR_DEVICE, "a fold dependency wait timed out");
+  if (f & kMedErrBit) return fail(ctx, FFA_ERR_DEVICE, "running median: a block bound failed");
   if (f) return fail(ctx, FFA_ERR_DEGENERATE, "a normalised series had zero or non-finite variance");
   return FFA_OK;
 }

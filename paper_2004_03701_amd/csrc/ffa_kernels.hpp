@@ -79,6 +79,14 @@ inline hipError_t set_lds_limit_once(const void* kernel, int bytes, bool* done) 
 // Sets a flag word to zero with a kernel (graph-capture friendly).
 hipError_t launch_clear_flag(int32_t* flag, hipStream_t stream);
 
+// De-reddening by a running median (Sec. 5.2) of one series of n samples of
+// `dtype`: out[i] = x[i] - the median of the `window` (odd) samples centred on
+// i, cut at the ends, stored as out_dtype. An internal bound that cannot fail
+// for a well-formed launch ORs kMedErrBit into *err.
+constexpr int32_t kMedErrBit = 8;
+hipError_t launch_running_median(const void* x, int64_t n, int32_t dtype, int32_t window,
+                                 void* out, int32_t out_dtype, int32_t* err, hipStream_t stream);
+
 // Bytes of the static device workspace of ffa_search_noalloc (one per device),
 // and the offset in it of the status word (the first 256 bytes hold it; the
 // rest is laid out per call).

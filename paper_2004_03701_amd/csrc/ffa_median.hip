@@ -1,0 +1,411 @@
+// De-reddening by a running median (Sec. 5.2): out[i] = x[i] - med[i], med[i]
+// the median of the window of 2h + 1 samples centred on i, cut at the ends
+// of the series; the median of n samples is their k-th smallest value,
+// k = (n - 1) / 2 (at the ends, for even n, the lower middle value). The
+// result is exact: the median is one of the samples and the difference is
+// one FP32 subtraction.
+//
+// One workgroup takes a block of B consecutive outputs (B <= (min(n, h + 1)
+// + 1) / 2). Their windows all contain the core C = [s(i1 - 1), e(i0)), and
+// each window adds at most B - 1 samples to it, so the k-th smallest of a
+// window lies between the (k - extra)-th and the k-th smallest of C. The
+// workgroup
+//   1. finds the two bounding values lo and hi of C by radix selection on
+//      order-preserving 32-bit keys (four 8-bit digits);
+//   2. keeps every sample of the union of the windows whose key lies strictly
+//      between them as a candidate (at most 4 B of them whatever the ties:
+//      samples equal to a bound are only counted) and sorts the candidates
+//      by (key, index) in LDS;
+//   3. lets each lane of one wave slide a sub-block of outputs: the counts
+//      of window samples below lo, equal to lo and strictly between the
+//      bounds change by at most two per output, and the position of the
+//      median among the sorted candidates moves by a few places; a lane's
+//      first position comes from one walk over the candidates that lie
+//      outside C (the others are in every window).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ffa.h"
+#include "ffa_kernels.hpp"
+
+namespace ffa {
+namespace {
+
+constexpr int kMedThreads = 512;
+constexpr int kMedBlockMax = 2048;          // outputs per workgroup
+constexpr int kMedCap = 4 * kMedBlockMax;   // candidates (a power of two)
+constexpr int kMedLanes = 64;               // lanes sliding the outputs
+
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <int DT>
+__device__ __forceinline__ float load_value(const void* base, int64_t i) {
+  if (DT == FFA_F32) return ((gptr<float>)base)[i];
+  const uint16_t b = ((gptr<uint16_t>)base)[i];
+  if (DT == FFA_BF16) return __uint_as_float(static_cast<uint32_t>(b) << 16);
+  _Float16 h;
+  __builtin_memcpy(&h, &b, 2);
+  return static_cast<float>(h);
+}
+
+// Order-preserving key of a value (-0 taken as +0, so equal values have equal
+// keys), and back.
+__device__ __forceinline__ uint32_t key_of(float v) {
+  uint32_t u = __float_as_uint(v);
+  if (u == 0x80000000u) u = 0;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float value_of(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+template <int DT>
+__device__ __forceinline__ uint32_t key_at(const void* x, int64_t i) {
+  return key_of(load_value<DT>(x, i));
+}
+
+// The key of rank `rank` (0-based) among the keys of x[c0, c1), by radix
+// selection, one 8-bit digit per pass from the top. All threads return it.
+template <int DT>
+__device__ uint32_t select_key(const void* x, int64_t c0, int64_t c1, int64_t rank, int* hist) {
+  __shared__ uint32_t s_prefix;
+  __shared__ int64_t s_rank;
+  if (threadIdx.x == 0) {
+    s_prefix = 0;
+    s_rank = rank;
+  }
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    for (int b = threadIdx.x; b < 256; b += kMedThreads) hist[b] = 0;
+    __syncthreads();
+    const uint32_t prefix = s_prefix;
+    const uint32_t mask = pass == 0 ? 0u : (0xffffffffu << (32 - 8 * pass));
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kMedThreads) {
+      const uint32_t k = key_at<DT>(x, i);
+      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      // the digit whose cumulative count passes the rank: lane l holds bins
+      // 4l .. 4l + 3
+      const int l = threadIdx.x;
+      int c[4], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = hist[4 * l + q];
+        tot += c[q];
+      }
+      int incl = tot;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d, 64);
+        if (l >= d) incl += u;
+      }
+      const int64_t r = s_rank;
+      int64_t before = incl - tot;
+      if (before <= r && r < incl) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (before <= r && r < before + c[q]) {
+            s_prefix = prefix | ((uint32_t)(4 * l + q) << shift);
+            s_rank = r - before;
+          }
+          before += c[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t key = s_prefix;
+  __syncthreads();  // every thread has read it before a later call resets it
+  return key;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, int64_t n,
+                                                                int32_t h, int32_t B, void* out,
+                                                                int32_t out_dtype, int32_t* err) {
+  __shared__ unsigned long long cand[kMedCap];  // (key << 32) | index - us, sorted
+  __shared__ int edge_pos[2 * kMedBlockMax];     // sorted positions of candidates outside C
+  __shared__ uint32_t lk[kMedBlockMax];          // keys of the samples that leave
+  __shared__ uint32_t ek[kMedBlockMax];          // keys of the samples that enter
+  __shared__ float ybuf[kMedBlockMax];
+  __shared__ int hist[256];
+  __shared__ int s_cnt, s_nedge, s_lo_rank, s_hi_rank;
+  __shared__ int s_cb, s_clo, s_cs;
+
+  const int64_t i0 = (int64_t)blockIdx.x * B;
+  const int64_t i1 = i0 + B < n ? i0 + B : n;
+  const int nb = (int)(i1 - i0);
+  auto ws = [&](int64_t i) { return i - h > 0 ? i - h : (int64_t)0; };
+  auto we = [&](int64_t i) { return i + h + 1 < n ? i + h + 1 : n; };
+  const int64_t cs = ws(i1 - 1), ce = we(i0);  // core
+  const int64_t us = ws(i0), ue = we(i1 - 1);  // union
+  const int64_t cn = ce - cs;
+
+  // 1. ranks of the bounds within C
+  if (threadIdx.x == 0) {
+    s_lo_rank = 0x7fffffff;
+    s_hi_rank = -1;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb; j += kMedThreads) {
+    const int64_t i = i0 + j;
+    const int64_t cnt = we(i) - ws(i);
+    const int64_t k = (cnt - 1) / 2;
+    atomicMin(&s_lo_rank, (int)(k - (cnt - cn)));
+    atomicMax(&s_hi_rank, (int)k);
+  }
+  __syncthreads();
+  const int lo_rank = s_lo_rank, hi_rank = s_hi_rank;
+  if (lo_rank < 0 || hi_rank >= cn) {  // the block is too long for its windows
+    if (threadIdx.x == 0) atomicOr(err, kMedErrBit);
+    return;
+  }
+  const uint32_t lo = select_key<DT>(x, cs, ce, lo_rank, hist);
+  const uint32_t hi = select_key<DT>(x, cs, ce, hi_rank, hist);
+
+  // 2. candidates (lo < key < hi) of the union, and the counts of window i0
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    s_cb = s_clo = s_cs = 0;
+  }
+  __syncthreads();
+  {
+    int cb = 0, clo = 0, csn = 0;
+    const int64_t w0 = ws(i0), w1 = we(i0);
+    for (int64_t i = us + threadIdx.x; i < ue; i += kMedThreads) {
+      const uint32_t k = key_at<DT>(x, i);
+      const bool in0 = i >= w0 && i < w1;
+      if (k < lo) {
+        cb += in0;
+      } else if (k == lo) {
+        clo += in0;
+      } else if (k < hi) {
+        csn += in0;
+        const int slot = atomicAdd(&s_cnt, 1);
+        if (slot < kMedCap) cand[slot] = ((unsigned long long)k << 32) | (uint32_t)(i - us);
+      }
+    }
+    atomicAdd(&s_cb, cb);
+    atomicAdd(&s_clo, clo);
+    atomicAdd(&s_cs, csn);
+  }
+  // keys of the samples that leave and enter the windows of the block
+  const int64_t l0 = ws(i0), e0 = we(i0);
+  const int nl = (int)(ws(i1 - 1) - l0), ne = (int)(we(i1 - 1) - e0);
+  for (int j = threadIdx.x; j < nl; j += kMedThreads) lk[j] = key_at<DT>(x, l0 + j);
+  for (int j = threadIdx.x; j < ne; j += kMedThreads) ek[j] = key_at<DT>(x, e0 + j);
+  __syncthreads();
+  const int ncand = s_cnt;
+  if (ncand > kMedCap) {  // cannot happen: at most 2 B from C and 2 B outside it
+    if (threadIdx.x == 0) atomicOr(err, kMedErrBit);
+    return;
+  }
+  int np2 = 1;
+  while (np2 < ncand) np2 <<= 1;
+  for (int j = ncand + threadIdx.x; j < np2; j += kMedThreads) cand[j] = ~0ull;
+  __syncthreads();
+  // bitonic sort of the candidates by (key, index)
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < (np2 >> 1); t += kMedThreads) {
+        const int a = 2 * t - (t & (stride - 1));
+        const int b = a + stride;
+        const bool up = (a & size) == 0;
+        const unsigned long long va = cand[a], vb = cand[b];
+        if ((va > vb) == up) {
+          cand[a] = vb;
+          cand[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // sorted positions of the candidates outside C, ascending
+  if (threadIdx.x == 0) s_nedge = 0;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int base = 0;
+    for (int j0 = 0; j0 < ncand; j0 += 64) {
+      const int j = j0 + (int)threadIdx.x;
+      bool outside = false;
+      if (j < ncand) {
+        const int64_t idx = us + (int64_t)(uint32_t)cand[j];
+        outside = idx < cs || idx >= ce;
+      }
+      const unsigned long long bal = __ballot(outside);
+      const int before = __popcll(bal & ((1ull << threadIdx.x) - 1ull));
+      if (outside) edge_pos[base + before] = j;
+      base += __popcll(bal);
+    }
+    if (threadIdx.x == 0) s_nedge = base;
+  }
+  __syncthreads();
+  const int nedge = s_nedge;
+
+  // 3. one wave slides the outputs, each lane a sub-block
+  if (threadIdx.x < kMedLanes) {
+    const int lane = threadIdx.x;
+    const int sb = (nb + kMedLanes - 1) / kMedLanes;
+    const int j0 = lane * sb, j1 = min(nb, j0 + sb);
+    if (j0 < j1) {
+      const int64_t ia = i0 + j0;
+      // counts for window ia: window i0 minus what left, plus what entered
+      int cb = s_cb, clo = s_clo, csn = s_cs;
+      const int nleft = (int)(ws(ia) - l0), nent = (int)(we(ia) - e0);
+      for (int q = 0; q < nleft; ++q) {
+        const uint32_t k = lk[q];
+        cb -= k < lo;
+        clo -= k == lo;
+        csn -= (k > lo && k < hi);
+      }
+      for (int q = 0; q < nent; ++q) {
+        const uint32_t k = ek[q];
+        cb += k < lo;
+        clo += k == lo;
+        csn += (k > lo && k < hi);
+      }
+      int64_t s = ws(ia), e = we(ia);
+      auto member = [&](int pos) {
+        const int64_t idx = us + (int64_t)(uint32_t)cand[pos];
+        return idx >= s && idx < e;
+      };
+      // first position: walk the candidates outside C in sorted order; the
+      // candidates between two non-members are all members
+      int m = ncand, r = 0;
+      int64_t t0 = (e - s - 1) / 2 - cb - clo;
+      if (t0 >= 0 && t0 < csn) {
+        int prev = 0, below = 0;
+        m = -1;
+        for (int q = 0; q < nedge; ++q) {
+          const int pq = edge_pos[q];
+          if (member(pq)) continue;
+          if (below + (pq - prev) > t0) {
+            m = prev + (int)(t0 - below);
+            break;
+          }
+          below += pq - prev;
+          prev = pq + 1;
+        }
+        if (m < 0) m = prev + (int)(t0 - below);
+        r = (int)t0;
+      } else {
+        m = 0;  // the answer is a bound; r counts members below m = 0
+        r = 0;
+      }
+      for (int j = j0; j < j1; ++j) {
+        const int64_t i = i0 + j;
+        if (j > j0) {
+          const int64_t s2 = ws(i), e2 = we(i);
+          const unsigned long long cm = m < ncand ? cand[m] : ~0ull;
+          if (s2 > s) {  // sample s leaves
+            const uint32_t k = lk[s - l0];
+            if (k < lo) {
+              --cb;
+            } else if (k == lo) {
+              --clo;
+            } else if (k < hi) {
+              --csn;
+              const unsigned long long ck = ((unsigned long long)k << 32) | (uint32_t)(s - us);
+              if (ck < cm) --r;
+            }
+          }
+          if (e2 > e) {  // sample e enters
+            const uint32_t k = ek[e - e0];
+            if (k < lo) {
+              ++cb;
+            } else if (k == lo) {
+              ++clo;
+            } else if (k < hi) {
+              ++csn;
+              const unsigned long long ck = ((unsigned long long)k << 32) | (uint32_t)(e - us);
+              if (ck < cm) ++r;
+            }
+          }
+          s = s2;
+          e = e2;
+        }
+        const int64_t k = (e - s - 1) / 2;
+        uint32_t mk;
+        if (k < cb) {  // cannot happen: lo bounds the median from below
+          atomicOr(err, kMedErrBit);
+          mk = lo;
+        } else if (k < cb + clo) {
+          mk = lo;
+        } else if (k - cb - clo >= csn) {
+          mk = hi;
+        } else {
+          const int t = (int)(k - cb - clo);
+          // move to the member with t members before it (r counts the
+          // members before position m)
+          for (;;) {
+            if (r > t) {
+              --m;
+              if (member(m)) --r;
+              continue;
+            }
+            if (m < ncand && member(m)) {
+              if (r == t) break;
+              ++r;
+            }
+            ++m;
+          }
+          mk = (uint32_t)(cand[m] >> 32);
+        }
+        const float xi = load_value<DT>(x, i);
+        ybuf[j] = xi - value_of(mk);
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb; j += kMedThreads) {
+    const float v = ybuf[j];
+    if (out_dtype == FFA_F32) {
+      static_cast<float*>(out)[i0 + j] = v;
+    } else if (out_dtype == FFA_BF16) {
+      uint32_t u = __float_as_uint(v);
+      uint16_t b;
+      if ((u & 0x7fffffffu) > 0x7f800000u)
+        b = static_cast<uint16_t>((u >> 16) | 0x40u);
+      else
+        b = static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+      static_cast<uint16_t*>(out)[i0 + j] = b;
+    } else {
+      _Float16 hv = static_cast<_Float16>(v);
+      uint16_t b;
+      __builtin_memcpy(&b, &hv, 2);
+      static_cast<uint16_t*>(out)[i0 + j] = b;
+    }
+  }
+}
+
+}  // namespace
+
+int32_t median_block(int64_t n, int32_t window) {
+  const int64_t h = window / 2;
+  int64_t b = ((n < h + 1 ? n : h + 1) + 1) / 2;
+  if (b > kMedBlockMax) b = kMedBlockMax;
+  return b < 1 ? 1 : (int32_t)b;
+}
+
+hipError_t launch_running_median(const void* x, int64_t n, int32_t dtype, int32_t window,
+                                 void* out, int32_t out_dtype, int32_t* err, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int32_t B = median_block(n, window);
+  const int64_t blocks = (n + B - 1) / B;
+  const int32_t h = window / 2;
+  if (dtype == FFA_BF16)
+    hipLaunchKernelGGL(k_running_median<FFA_BF16>, dim3((unsigned)blocks), dim3(kMedThreads), 0,
+                       stream, x, n, h, B, out, out_dtype, err);
+  else if (dtype == FFA_F16)
+    hipLaunchKernelGGL(k_running_median<FFA_F16>, dim3((unsigned)blocks), dim3(kMedThreads), 0,
+                       stream, x, n, h, B, out, out_dtype, err);
+  else
+    hipLaunchKernelGGL(k_running_median<FFA_F32>, dim3((unsigned)blocks), dim3(kMedThreads), 0,
+                       stream, x, n, h, B, out, out_dtype, err);
+  return hipGetLastError();
+}
+
+}  // namespace ffa
