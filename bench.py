@@ -56,6 +56,9 @@ def parse():
                     help="1: also time peak detection (Sec. 5.5) on the headline variant's "
                          "periodograms, reported apart from the step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--median", type=int, default=1,
+                    help="1: also time the running-median de-reddening (Sec. 5.2) of the "
+                         "workload-2 series, reported apart from the step")
     ap.add_argument("--workload", default="batch", choices=["batch", "uneven", "single"])
     ap.add_argument("--autotune", type=int, default=0,
                     help="autotune the tiling on --tune-series series first (the default tiling "
@@ -248,8 +251,28 @@ def cpu_baseline(seconds, nsamp):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": rows / dt, "unit": "profiles/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{done} whole series of 2^{int(math.log2(nsamp))} samples, full plan "
                       f"({rows} profiles x 9 widths) in {dt:.1f} s, FP64 depth-first FFA"}
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main_uneven(a):
@@ -304,6 +327,41 @@ def main_uneven(a):
         "variants": out}), flush=True)
 
 
+def bench_median(ffa, ctx, torch, a):
+    """Running-median de-reddening (Sec. 5.2) of the workload-2 series
+    (9,375,000 samples, 78,125-sample window), apart from the step: kernel
+    time from HIP events, algorithmic bytes (one read and one write of the
+    series, FP32) against 8 TB/s, and the oracle on the same series."""
+    import synth
+    x, cfg, _ = synth.workload2()
+    dev = torch.from_numpy(x).cuda()
+    out = torch.empty_like(dev)
+    for _ in range(2):
+        ffa.ffa_running_median(ctx, dev, cfg.median_window, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        ffa.ffa_running_median(ctx, dev, cfg.median_window, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    ms = e0.elapsed_time(e1) / reps
+    alg = 8 * x.size
+    res = {"samples": int(x.size), "window": cfg.median_window, "ms_per_call": ms,
+           "samples_per_s": x.size / (ms * 1e-3), "alg_bytes": alg,
+           "alg_GBps": alg / (ms * 1e-3) / 1e9, "frac_of_hbm": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if a.cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.running_median(x, cfg.median_window)
+        res["cpu_oracle_ms"] = 1e3 * (time.perf_counter() - t0)
+    log(f"running median: {ms:.3f} ms per call")
+    del dev, out
+    return res
+
+
 def main_single(a):
     """Single series (workloads 1 and 2): launch- and latency-bound searches,
     timed as eager per-pass launches, as hipGraph replays, and as graph
@@ -318,10 +376,10 @@ def main_single(a):
         x, cfg, _ = make()
         dev = torch.from_numpy(x.astype(np.float32)).cuda()
         prm = ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
-                              cfg.bins_max, cfg.widths)
+                              cfg.bins_max, cfg.widths, median_window=cfg.median_window)
         rows = ffa.ffa_plan_rows(prm, dev.numel())
         snr = torch.empty((rows, len(cfg.widths)), dtype=torch.float32, device="cuda")
-        res = {"samples": int(dev.numel()), "profiles": rows}
+        res = {"samples": int(dev.numel()), "profiles": rows, "median_window": cfg.median_window}
         for name, persistent, graph in (("eager", 0, False), ("graph", 0, True),
                                         ("persistent_graph", 1, True)):
             ffa.ffa_set_tiling(ctx, persistent=persistent)
@@ -340,7 +398,7 @@ def main_single(a):
         if a.cpu_baseline:
             t0 = time.perf_counter()
             oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
-                          cfg.bins_max, cfg.widths)
+                          cfg.bins_max, cfg.widths, median_window=cfg.median_window)
             dt = time.perf_counter() - t0
             res["cpu_oracle"] = {"ms_per_search": 1e3 * dt, "profiles_per_s": rows / dt,
                                  "cores": int(os.environ.get("OMP_NUM_THREADS",
@@ -454,9 +512,11 @@ def main():
         profiles = rows1 * a.series
         esize = 4 if tdt is None else 2  # the folded (downsampled) series: the storage type
         alg_bytes = a.series * (int(bins.sum()) * esize + rows1 * len(cfg.widths) * 4)
+        alg_bytes_f32 = a.series * (int(bins.sum()) * 4 + rows1 * len(cfg.widths) * 4)
         fold_ms = tm["fold_ms"] / a.steps if tm["fold_launches"] else None
         res = {"ms_per_step": ms, "profiles_per_s": profiles / (ms * 1e-3),
-               "profiles": profiles, "alg_bytes_fold": alg_bytes, "alg_ops_fold": alg_ops,
+               "profiles": profiles, "alg_bytes_fold": alg_bytes,
+               "alg_bytes_fold_f32": alg_bytes_f32, "alg_ops_fold": alg_ops,
                "timing": tm,
                "tiling": tiling, "eager_ms_per_step": 1e3 * wall_eager / a.steps,
                "graph_ms_per_step": graph_ms}
@@ -473,6 +533,9 @@ def main():
         del series, xs, snr
         torch.cuda.empty_cache()
     ranges_res = bench_ranges(ffa, ctx, x32, nsamp, cfg, a) if a.ranges else None
+    del x32
+    torch.cuda.empty_cache()
+    median_res = bench_median(ffa, ctx, torch, a) if a.median else None
     head = variants[0]
     r = results[head]
     out = {
@@ -500,6 +563,10 @@ def main():
                            "frac": ach / HBM_PEAK_GBS,
                            "traffic": (tb / (r["fold_ms_per_step"] * 1e-3) / 1e9) if tb else None,
                            "kernel": "k_ffa_pass (all fold launches of a step)",
+                           "bytes_per_input_sample": 4 if head == "f32" else 2,
+                           "frac_at_fp32_bytes": (r["alg_bytes_fold_f32"] /
+                                                  (r["fold_ms_per_step"] * 1e-3) / 1e9 /
+                                                  HBM_PEAK_GBS),
                            "fold_ms_per_step": r["fold_ms_per_step"],
                            "copy_GBps": copy_gbs, "frac_of_copy": ach / copy_gbs,
                            "alu": {"achieved": r["fold_alg_Tops"], "peak": VALU_PEAK_TOPS,
@@ -509,6 +576,8 @@ def main():
         out["peaks"] = r["peaks"]
     if ranges_res:
         out["ranges"] = ranges_res
+    if median_res:
+        out["median"] = median_res
     out["variants"] = {k: {kk: vv for kk, vv in v.items() if kk not in ("timing", "peaks")}
                        for k, v in results.items()}
     if "f32" in results and head != "f32":

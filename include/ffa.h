@@ -70,7 +70,12 @@ typedef struct ffa_ctx ffa_ctx;
  *                half the bytes of an FP32 one); the fold converts them on
  *                load, and every sum from there on is FP32. With FP16 storage
  *                the downsampled samples must fit FP16 (as they do for a
- *                normalised series). */
+ *                normalised series).
+ *   median_window  0: no de-reddening; otherwise an odd number of samples:
+ *                the running median over that window is subtracted from the
+ *                series first (Sec. 5.2; see ffa_running_median), the result
+ *                kept in the storage type, and normalisation (if asked) and
+ *                everything after it use the de-reddened series. */
 typedef struct {
   double tsamp;
   double period_min;
@@ -81,6 +86,7 @@ typedef struct {
   int32_t num_widths;
   int32_t normalise;
   int32_t dtype;
+  int32_t median_window;
 } ffa_search_params;
 
 /* Creates a context on HIP device `device`. *out receives the handle. */
@@ -144,7 +150,8 @@ ffa_status ffa_search_batch(ffa_ctx* ctx, int32_t nseries, const void* const* se
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid allocation): ffa_search with no
  * device allocation of its own. Arguments, outputs and errors as ffa_search.
- * Every intermediate buffer (the tables of the search, the statistics, the
+ * Every intermediate buffer (the tables of the search, the de-reddened copy
+ * of the series when params->median_window > 0, the statistics, the
  * downsampled series and the scratch rows between passes) is carved from a
  * static device workspace of FFA_NOALLOC_WORKSPACE_BYTES that each device the
  * library runs on holds until the process ends; the call allocates no device
@@ -331,6 +338,8 @@ typedef struct {
   int64_t downsampled_samples; /* samples written by the downsampler */
   double peaks_ms;             /* peak-detection kernels (Sec. 5.5) */
   int64_t peaks_launches;      /* timed peak-detection steps: control points, fit, selection */
+  double median_ms;            /* running-median de-reddening kernels (Sec. 5.2) */
+  int64_t median_launches;
 } ffa_kernel_times;
 
 /* Turns per-kernel timing on (1) or off (0) for the calls that follow. */

@@ -268,17 +268,20 @@ class Periodogram:
 
 def search(x: np.ndarray, tsamp: float, period_min: float, period_max: float, bins_min: int,
            bins_max: int, widths: Sequence[int], normalise: bool = True, brute: bool = False,
-           octave_subset: Optional[Sequence[int]] = None) -> Periodogram:
-    """Periodogram of one series: normalise (Sec. 5.2), then for every
-    pseudo-octave downsample the original (Sec. 5.3), fold at every p
-    (Sec. 2) and take the boxcar S/N of every kept row (Sec. 5.4, 5.5).
-    Rows are in (octave, p, s) order, which is ascending period."""
+           octave_subset: Optional[Sequence[int]] = None, median_window: int = 0) -> Periodogram:
+    """Periodogram of one series: subtract the running median if a window is
+    given, normalise (Sec. 5.2), then for every pseudo-octave downsample the
+    original (Sec. 5.3), fold at every p (Sec. 2) and take the boxcar S/N of
+    every kept row (Sec. 5.4, 5.5). Rows are in (octave, p, s) order, which is
+    ascending period."""
     widths = [int(w) for w in widths]
     if not widths or any(w < 1 for w in widths) or any(b <= a for a, b in zip(widths, widths[1:])):
         raise PlanError("widths must be strictly increasing and >= 1")
     if widths[-1] >= bins_min:
         raise PlanError("widest boxcar must be narrower than bins_min")
     xd = np.asarray(x, dtype=np.float64)
+    if median_window:
+        xd = running_median(xd, median_window)[0]
     if normalise:
         mu, sigma = normalise_stats(xd)
         if not np.isfinite(sigma) or sigma == 0.0:

@@ -53,6 +53,7 @@ class ffa_search_params(ctypes.Structure):
         ("num_widths", ctypes.c_int32),
         ("normalise", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
+        ("median_window", ctypes.c_int32),
     ]
 
 
@@ -76,6 +77,8 @@ class ffa_kernel_times(ctypes.Structure):
         ("downsampled_samples", ctypes.c_int64),
         ("peaks_ms", ctypes.c_double),
         ("peaks_launches", ctypes.c_int64),
+        ("median_ms", ctypes.c_double),
+        ("median_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -168,12 +171,12 @@ def _check(st: int, ctx=None):
 
 def make_params(tsamp: float, period_min: float, period_max: float, bins_min: int,
                 bins_max: int, widths: Sequence[int], normalise: bool = True,
-                dtype: int = FFA_F32) -> ffa_search_params:
+                dtype: int = FFA_F32, median_window: int = 0) -> ffa_search_params:
     """Parameter struct; keeps its widths array alive as an attribute."""
     w = (ctypes.c_int32 * len(widths))(*[int(v) for v in widths])
     prm = ffa_search_params(float(tsamp), float(period_min), float(period_max), int(bins_min),
                             int(bins_max), ctypes.cast(w, ctypes.POINTER(ctypes.c_int32)),
-                            len(widths), 1 if normalise else 0, int(dtype))
+                            len(widths), 1 if normalise else 0, int(dtype), int(median_window))
     prm._widths_keepalive = w
     return prm
 

@@ -113,6 +113,19 @@ struct Job {
   int32_t max_counters = 0;
   DevBuf series, oct, xf, scales, tiles, need, src_rows;
   int32_t stats_blocks = 0;
+  // Series de-reddened first (Sec. 5.2): the running median of series `index`
+  // goes to element `off` of the de-reddened buffer, which the series table
+  // then points at.
+  struct Median {
+    int32_t index;
+    const void* src;
+    int64_t nsamp;
+    int32_t window;
+    int64_t off;
+  };
+  std::vector<Median> medians;
+  int64_t dered_elems = 0;
+  DevBuf dered;
 };
 
 // Host copies of a job's device tables, before they are placed on the device.
@@ -135,6 +148,7 @@ struct JobTables {
   const TileDesc* tiles = nullptr;
   const int32_t* src_rows = nullptr;
   const int32_t* need = nullptr;
+  void* dered = nullptr;  // de-reddened series (storage type)
 };
 
 // Device workspace a job's launches use besides its tables.
@@ -160,7 +174,7 @@ struct NaJob {
   size_t off_series = 0, off_oct = 0, off_xf = 0, off_scales = 0, off_tiles = 0,
          off_src_rows = 0;
   // workspace layout past the tables
-  size_t off_stats = 0, off_norm = 0, off_flag = 0, off_partials = 0, off_ds = 0,
+  size_t off_stats = 0, off_norm = 0, off_flag = 0, off_partials = 0, off_dered = 0, off_ds = 0,
          off_scr0 = 0, off_scr1 = 0;
 };
 
@@ -193,7 +207,7 @@ struct PeakPlan {
 struct NaJob;
 
 struct TimedLaunch {
-  int kind;  // 0 stats, 1 downsample, 2 fold, 3 peak detection
+  int kind;  // 0 stats, 1 downsample, 2 fold, 3 peak detection, 4 running median
   hipEvent_t start, stop;
 };
 
@@ -317,6 +331,10 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       return fail(ctx, FFA_ERR_INVALID_ARG, "more than 128 pseudo-octaves: period range too wide");
     sd[i].ptr = series[i];
     sd[i].nsamp = nsamp[i];
+    if (a.median_window > 0) {
+      job->medians.push_back(Job::Median{i, series[i], nsamp[i], a.median_window, job->dered_elems});
+      job->dered_elems += nsamp[i];
+    }
     sd[i].chunk0 = chunk;
     sd[i].oct0 = (int32_t)od.size();
     sd[i].noct = (int32_t)pl.oct.size();
@@ -442,8 +460,22 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
   return FFA_OK;
 }
 
+size_t elem_bytes(int32_t dtype) { return dtype == FFA_F32 ? 4 : 2; }
+
+// Points the series table of de-reddened series at their copies (base: the
+// de-reddened buffer).
+void point_at_dered(const Job& job, void* base, HostTables* ht) {
+  for (const Job::Median& m : job.medians)
+    ht->sd[m.index].ptr = static_cast<unsigned char*>(base) + m.off * elem_bytes(job.dtype);
+}
+
 // Places a job's tables in its own device buffers.
-ffa_status upload_job(ffa_ctx* ctx, Job* job, const HostTables& ht) {
+ffa_status upload_job(ffa_ctx* ctx, Job* job, HostTables& ht) {
+  if (job->dered_elems > 0) {
+    HIP_TRY(ctx, job->dered.reserve((size_t)job->dered_elems * elem_bytes(job->dtype) + 16),
+            "allocate de-reddened series");
+    point_at_dered(*job, job->dered.ptr, &ht);
+  }
   HIP_TRY(ctx, upload(job->series, ht.sd), "upload series table");
   HIP_TRY(ctx, upload(job->oct, ht.od), "upload octave table");
   HIP_TRY(ctx, upload(job->xf, ht.xf), "upload transform table");
@@ -463,6 +495,7 @@ JobTables job_tables(const Job& job) {
   t.tiles = job.tiles.as<TileDesc>();
   t.src_rows = job.src_rows.as<int32_t>();
   t.need = job.need.as<int32_t>();
+  t.dered = job.dered.ptr;
   return t;
 }
 
@@ -547,6 +580,14 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
     ctx->times.downsampled_samples += job.ds_total;
   }
   const SeriesDev* sd = tb.series;
+  for (const Job::Median& m : job.medians) {
+    TimedScope ts(ctx, 4, stream, timed);
+    HIP_TRY(ctx, launch_running_median(m.src, m.nsamp, job.dtype, m.window,
+                                       static_cast<unsigned char*>(tb.dered) +
+                                           m.off * elem_bytes(job.dtype),
+                                       job.dtype, ws.flag, stream),
+            "running median kernel");
+  }
   if (job.any_normalise) {
     TimedScope ts(ctx, 0, stream, timed);
     HIP_TRY(ctx, launch_stats(sd, job.nseries, job.dtype, job.stats_blocks, ws.partials, ws.stats,
@@ -625,7 +666,8 @@ std::string job_key(int32_t nseries, const void* const* series, const int64_t* n
     << tiling.persistent << ',' << tiling.waves << ',' << tiling.range_waves << '|';
   for (int i = 0; i < nseries; ++i)
     k << series[i] << ',' << row_offset[i] << ',' << params[i].normalise << ','
-      << params[i].dtype << ',' << plan_key(params[i], nsamp[i]) << ';';
+      << params[i].dtype << ',' << params[i].median_window << ','
+      << plan_key(params[i], nsamp[i]) << ';';
   return k.str();
 }
 
@@ -826,6 +868,8 @@ ffa_status build_na_job(ffa_ctx* ctx, const void* series, int64_t nsamp,
     if (st != FFA_OK) return st;
     const Job& job = *nj->job;
     nj->packed.assign(kNoAllocHeader, 0);
+    // the de-reddened copies sit past the tables, whose size does not depend
+    // on the pointers: lay out once with the pointers unset, then set them
     pack_table(&nj->packed, &nj->off_series, ht.sd);
     pack_table(&nj->packed, &nj->off_oct, ht.od);
     pack_table(&nj->packed, &nj->off_xf, ht.xf);
@@ -839,14 +883,20 @@ ffa_status build_na_job(ffa_ctx* ctx, const void* series, int64_t nsamp,
     o = align256(o + 2 * sizeof(float));
     nj->off_partials = o;
     o = align256(o + (size_t)job.stats_blocks * 2 * sizeof(double));
+    nj->off_dered = o;
+    o = align256(o + (size_t)job.dered_elems * elem_bytes(job.dtype) + 16);
     nj->off_ds = o;
-    o = align256(o + (size_t)job.ds_total * (job.dtype == FFA_F32 ? 4 : 2) + 16);
+    o = align256(o + (size_t)job.ds_total * elem_bytes(job.dtype) + 16);
     nj->off_scr0 = o;
     o = align256(o + (size_t)job.scr_cells * 4 + 16);
     nj->off_scr1 = o;
     o = align256(o + (size_t)job.scr_cells * 4 + 16);
     if (round == 1 && o > kNoAllocBytes)
       return fail(ctx, FFA_ERR_DEVICE, "ffa_search_noalloc: workspace layout overflow");
+    if (round == 1 && !job.medians.empty()) {
+      point_at_dered(job, static_cast<unsigned char*>(ctx->na_ws) + nj->off_dered, &ht);
+      memcpy(nj->packed.data() + nj->off_series, ht.sd.data(), ht.sd.size() * sizeof(SeriesDev));
+    }
   }
   return FFA_OK;
 }
@@ -1029,6 +1079,7 @@ ffa_status ffa_search_noalloc(ffa_ctx* ctx, const void* series, int64_t nsamp,
   tb.scales = reinterpret_cast<const float*>(ws + nj->off_scales);
   tb.tiles = reinterpret_cast<const TileDesc*>(ws + nj->off_tiles);
   tb.src_rows = reinterpret_cast<const int32_t*>(ws + nj->off_src_rows);
+  tb.dered = ws + nj->off_dered;
   Workspace w;
   w.stats = reinterpret_cast<double*>(ws + nj->off_stats);
   w.norm = reinterpret_cast<float*>(ws + nj->off_norm);
@@ -1312,6 +1363,9 @@ ffa_status ffa_read_timing(ffa_ctx* ctx, ffa_kernel_times* out, int32_t reset) {
     } else if (t.kind == 2) {
       ctx->times.fold_ms += ms;
       ctx->times.fold_launches += 1;
+    } else if (t.kind == 4) {
+      ctx->times.median_ms += ms;
+      ctx->times.median_launches += 1;
     } else {
       ctx->times.peaks_ms += ms;
       ctx->times.peaks_launches += 1;

@@ -63,6 +63,10 @@ ffa_status validate_params(const ffa_search_params& a, std::string* err) {
     *err = "unknown dtype";
     return FFA_ERR_INVALID_ARG;
   }
+  if (a.median_window < 0 || (a.median_window > 0 && a.median_window % 2 == 0)) {
+    *err = "median_window must be 0 (none) or odd";
+    return FFA_ERR_INVALID_ARG;
+  }
   return FFA_OK;
 }
 

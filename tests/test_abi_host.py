@@ -116,6 +116,10 @@ def test_parameter_validation():
     p = ffa.make_params(**good)
     p.dtype = 7
     assert status_of(lambda: ffa.ffa_plan_rows(p, 262144)) == ffa.FFA_ERR_INVALID_ARG
+    # the running-median window (Sec. 5.2) is 0 (none) or odd
+    assert status_of(rows(median_window=1001)) == ffa.FFA_OK
+    assert status_of(rows(median_window=1000)) == ffa.FFA_ERR_INVALID_ARG
+    assert status_of(rows(median_window=-1)) == ffa.FFA_ERR_INVALID_ARG
 
 
 def test_plan_export_capacity():

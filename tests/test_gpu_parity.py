@@ -122,7 +122,8 @@ def test_downsample(ctx, ds):
 
 def run_search(ctx, x, cfg, normalise=True, dtype=ffa.FFA_F32, tdtype=torch.float32):
     prm = ffa.make_params(cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min, cfg.bins_max,
-                          cfg.widths, normalise=normalise, dtype=dtype)
+                          cfg.widths, normalise=normalise, dtype=dtype,
+                          median_window=cfg.median_window)
     per, bins, snr = ffa.ffa_search(ctx, dev(x, tdtype), prm)
     torch.cuda.synchronize()
     return per, bins, snr.cpu().numpy()
@@ -231,12 +232,55 @@ def test_search_duty_width_grid(ctx):
 
 
 def test_search_workload2_full(ctx):
+    # red noise de-reddened in the search by the running median of 5 s
+    # (Sec. 5.2), then normalised and searched
     x, cfg, pulses = synth.workload2()
+    assert cfg.median_window == 78125
     per, bins, snr = run_search(ctx, x, cfg)
     ref = oracle.search(x, cfg.tsamp, cfg.period_min, cfg.period_max, cfg.bins_min,
-                        cfg.bins_max, cfg.widths)
+                        cfg.bins_max, cfg.widths, median_window=cfg.median_window)
     assert np.array_equal(per, ref.periods)
     assert snr_close(snr, ref.snr) < SNR_RTOL
+    # the brightest injected pulse stands out of the de-reddened periodogram
+    top = max(pulses, key=lambda q: q.amplitude)
+    near = np.abs(per / (top.period * cfg.tsamp) - 1.0) < 0.01
+    assert snr[near].max() > 7.0
+
+
+def test_batch_with_and_without_de_reddening(ctx):
+    # a batch mixing series with and without the running median (different
+    # windows), eager and replayed, and the single-series no-allocation search
+    # of one of them, against the oracle
+    g = synth.rng(21, 0)
+    n = 600_000
+    base = [synth.noise(n, g).astype(np.float64) + synth.red_noise(n, 0.3, g) for _ in range(3)]
+    xs = [b.astype(np.float32) for b in base]
+    windows = [0, 15625, 4001]
+    tsamp = 64e-6
+    params = [ffa.make_params(tsamp, 0.1, 2.0, 240, 259, synth.WIDTHS_DUTY, median_window=w)
+              for w in windows]
+    dev_x = [dev(x) for x in xs]
+    refs = [oracle.search(x, tsamp, 0.1, 2.0, 240, 259, synth.WIDTHS_DUTY, median_window=w)
+            for x, w in zip(xs, windows)]
+    snr, offs = ffa.ffa_search_batch(ctx, dev_x, params)
+    torch.cuda.synchronize()
+    got = snr.cpu().numpy()
+    for i, r in enumerate(refs):
+        assert snr_close(got[offs[i]:offs[i] + r.snr.shape[0]], r.snr) < SNR_RTOL, i
+    out = torch.full(snr.shape, -1.0, device="cuda")
+    for rep in range(2):
+        out.fill_(-1.0)
+        ffa.ffa_search_batch(ctx, dev_x, params, snr=out, row_offset=offs, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), got), rep
+        ffa.ffa_search_batch(ctx, dev_x[:1], params[:1])
+        torch.cuda.synchronize()
+    one = torch.full((refs[1].snr.shape[0], 9), -1.0, device="cuda")
+    ffa.ffa_search_noalloc(ctx, dev_x[1], params[1], one)
+    torch.cuda.synchronize()
+    assert np.array_equal(one.cpu().numpy(), got[offs[1]:offs[1] + refs[1].snr.shape[0]])
+    tm_before = ffa.ffa_read_timing(ctx, reset=False)
+    assert "median_ms" in tm_before
 
 
 def batch_inputs(n):
