@@ -10,8 +10,8 @@
 // each window adds at most B - 1 samples to it, so the k-th smallest of a
 // window lies between the (k - extra)-th and the k-th smallest of C. The
 // workgroup
-//   1. finds the two bounding values lo and hi of C by radix selection on
-//      order-preserving 32-bit keys (four 8-bit digits);
+//   1. finds the two bounding values lo and hi of C by one radix selection
+//      for both on order-preserving 32-bit keys (digits of 11, 11, 10 bits);
 //   2. keeps every sample of the union of the windows whose key lies strictly
 //      between them as a candidate (at most 4 B of them whatever the ties:
 //      samples equal to a bound are only counted) and sorts the candidates
@@ -31,7 +31,7 @@
 namespace ffa {
 namespace {
 
-constexpr int kMedThreads = 512;
+constexpr int kMedThreads = 1024;
 constexpr int kMedBlockMax = 2048;          // outputs per workgroup
 constexpr int kMedCap = 4 * kMedBlockMax;   // candidates (a power of two)
 constexpr int kMedLanes = 64;               // lanes sliding the outputs
@@ -65,61 +65,100 @@ __device__ __forceinline__ uint32_t key_at(const void* x, int64_t i) {
   return key_of(load_value<DT>(x, i));
 }
 
-// The key of rank `rank` (0-based) among the keys of x[c0, c1), by radix
-// selection, one 8-bit digit per pass from the top. All threads return it.
-template <int DT>
-__device__ uint32_t select_key(const void* x, int64_t c0, int64_t c1, int64_t rank, int* hist) {
-  __shared__ uint32_t s_prefix;
-  __shared__ int64_t s_rank;
-  if (threadIdx.x == 0) {
-    s_prefix = 0;
-    s_rank = rank;
-  }
-  for (int pass = 0; pass < 4; ++pass) {
-    const int shift = 24 - 8 * pass;
-    for (int b = threadIdx.x; b < 256; b += kMedThreads) hist[b] = 0;
-    __syncthreads();
-    const uint32_t prefix = s_prefix;
-    const uint32_t mask = pass == 0 ? 0u : (0xffffffffu << (32 - 8 * pass));
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kMedThreads) {
-      const uint32_t k = key_at<DT>(x, i);
-      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      // the digit whose cumulative count passes the rank: lane l holds bins
-      // 4l .. 4l + 3
-      const int l = threadIdx.x;
-      int c[4], tot = 0;
+// Calls f(i, key) for every sample i of x[a, b), each thread a share; the
+// aligned middle is read 16 bytes at a time (when x is 16-byte aligned).
+template <int DT, class F>
+__device__ __forceinline__ void for_each_key(const void* x, int64_t a, int64_t b, F&& f) {
+  constexpr int kPer = DT == FFA_F32 ? 4 : 8;  // samples per 16-byte load
+  int64_t va = (a + kPer - 1) / kPer * kPer, vb = b / kPer * kPer;
+  if (va > vb || (reinterpret_cast<uintptr_t>(x) & 15) != 0) va = vb = b;
+  for (int64_t i = a + threadIdx.x; i < va; i += kMedThreads) f(i, key_at<DT>(x, i));
+  for (int64_t i = vb + threadIdx.x; i < b; i += kMedThreads) f(i, key_at<DT>(x, i));
+  for (int64_t v = va / kPer + threadIdx.x; v < vb / kPer; v += kMedThreads) {
+    const uint4 w = reinterpret_cast<const uint4*>(x)[v];
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c[q] = hist[4 * l + q];
-        tot += c[q];
+    for (int q = 0; q < kPer; ++q) {
+      float val;
+      if (DT == FFA_F32) {
+        val = __uint_as_float(u[q]);
+      } else {
+        const uint16_t h16 = (uint16_t)(u[q / 2] >> (16 * (q % 2)));
+        if (DT == FFA_BF16) {
+          val = __uint_as_float((uint32_t)h16 << 16);
+        } else {
+          _Float16 hv;
+          __builtin_memcpy(&hv, &h16, 2);
+          val = (float)hv;
+        }
       }
+      f(v * kPer + q, key_of(val));
+    }
+  }
+}
+
+constexpr int kDigitBits[3] = {11, 11, 10};  // digits from the top of the key
+constexpr int kBins = 2048;
+
+// The keys of ranks r0 and r1 (0-based) among the keys of x[c0, c1), by one
+// radix selection for both: three digit passes, each counting the keys that
+// share the prefix found so far of either rank. All threads return them.
+template <int DT>
+__device__ void select_two(const void* x, int64_t c0, int64_t c1, int64_t r0, int64_t r1,
+                           int* hist /* 2 * kBins */, uint32_t* k0, uint32_t* k1) {
+  __shared__ uint32_t s_prefix[2];
+  __shared__ int64_t s_rank[2];
+  if (threadIdx.x == 0) {
+    s_prefix[0] = s_prefix[1] = 0;
+    s_rank[0] = r0;
+    s_rank[1] = r1;
+  }
+  int shift = 32;
+  for (int pass = 0; pass < 3; ++pass) {
+    const int bits = kDigitBits[pass];
+    const uint32_t mask = shift == 32 ? 0u : (0xffffffffu << shift);
+    shift -= bits;
+    for (int q = threadIdx.x; q < 2 * kBins; q += kMedThreads) hist[q] = 0;
+    __syncthreads();
+    const uint32_t p0 = s_prefix[0], p1 = s_prefix[1];
+    const uint32_t dmask = (1u << bits) - 1u;
+    const int sh = shift;
+    for_each_key<DT>(x, c0, c1, [&](int64_t, uint32_t k) {
+      const uint32_t d = (k >> sh) & dmask;
+      if ((k & mask) == p0) atomicAdd(&hist[d], 1);
+      if ((k & mask) == p1) atomicAdd(&hist[kBins + d], 1);
+    });
+    __syncthreads();
+    // wave w < 2 finds the digit of rank w: lane l holds bins 32 l .. 32 l + 31
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (w < 2) {
+      const int* hh = hist + w * kBins;
+      int tot = 0;
+      for (int q = 0; q < kBins / 64; ++q) tot += hh[(kBins / 64) * l + q];
       int incl = tot;
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
         const int u = __shfl_up(incl, d, 64);
         if (l >= d) incl += u;
       }
-      const int64_t r = s_rank;
+      const int64_t r = s_rank[w];
       int64_t before = incl - tot;
       if (before <= r && r < incl) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (before <= r && r < before + c[q]) {
-            s_prefix = prefix | ((uint32_t)(4 * l + q) << shift);
-            s_rank = r - before;
+        for (int q = 0; q < kBins / 64; ++q) {
+          const int c = hh[(kBins / 64) * l + q];
+          if (before <= r && r < before + c) {
+            s_prefix[w] = (w == 0 ? p0 : p1) | ((uint32_t)((kBins / 64) * l + q) << sh);
+            s_rank[w] = r - before;
           }
-          before += c[q];
+          before += c;
         }
       }
     }
     __syncthreads();
   }
-  const uint32_t key = s_prefix;
-  __syncthreads();  // every thread has read it before a later call resets it
-  return key;
+  *k0 = s_prefix[0];
+  *k1 = s_prefix[1];
+  __syncthreads();  // every thread has read them before a later call resets them
 }
 
 template <int DT>
@@ -131,7 +170,8 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
   __shared__ uint32_t lk[kMedBlockMax];          // keys of the samples that leave
   __shared__ uint32_t ek[kMedBlockMax];          // keys of the samples that enter
   __shared__ float ybuf[kMedBlockMax];
-  __shared__ int hist[256];
+  __shared__ int hist[2 * kBins];
+  __shared__ int s_lane[kMedLanes][3];  // counts of each sliding lane's first window
   __shared__ int s_cnt, s_nedge, s_lo_rank, s_hi_rank;
   __shared__ int s_cb, s_clo, s_cs;
 
@@ -163,8 +203,8 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
     if (threadIdx.x == 0) atomicOr(err, kMedErrBit);
     return;
   }
-  const uint32_t lo = select_key<DT>(x, cs, ce, lo_rank, hist);
-  const uint32_t hi = select_key<DT>(x, cs, ce, hi_rank, hist);
+  uint32_t lo, hi;
+  select_two<DT>(x, cs, ce, lo_rank, hi_rank, hist, &lo, &hi);
 
   // 2. candidates (lo < key < hi) of the union, and the counts of window i0
   if (threadIdx.x == 0) {
@@ -175,8 +215,7 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
   {
     int cb = 0, clo = 0, csn = 0;
     const int64_t w0 = ws(i0), w1 = we(i0);
-    for (int64_t i = us + threadIdx.x; i < ue; i += kMedThreads) {
-      const uint32_t k = key_at<DT>(x, i);
+    for_each_key<DT>(x, us, ue, [&](int64_t i, uint32_t k) {
       const bool in0 = i >= w0 && i < w1;
       if (k < lo) {
         cb += in0;
@@ -187,7 +226,7 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
         const int slot = atomicAdd(&s_cnt, 1);
         if (slot < kMedCap) cand[slot] = ((unsigned long long)k << 32) | (uint32_t)(i - us);
       }
-    }
+    });
     atomicAdd(&s_cb, cb);
     atomicAdd(&s_clo, clo);
     atomicAdd(&s_cs, csn);
@@ -242,6 +281,35 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
     }
     if (threadIdx.x == 0) s_nedge = base;
   }
+  // counts of each sliding lane's first window: window i0 minus the samples
+  // that left, plus those that entered, 16 threads per lane
+  for (int q = threadIdx.x; q < kMedLanes * 3; q += kMedThreads) (&s_lane[0][0])[q] = 0;
+  __syncthreads();
+  {
+    constexpr int kPer = kMedThreads / kMedLanes;
+    const int lane = threadIdx.x / kPer, part = threadIdx.x % kPer;
+    const int sb = (nb + kMedLanes - 1) / kMedLanes;
+    const int64_t ia = i0 + (int64_t)lane * sb;
+    if (lane * sb < nb) {
+      const int nleft = (int)(ws(ia) - l0), nent = (int)(we(ia) - e0);
+      int cb = 0, clo = 0, csn = 0;
+      for (int q = part; q < nleft; q += kPer) {
+        const uint32_t k = lk[q];
+        cb -= k < lo;
+        clo -= k == lo;
+        csn -= (k > lo && k < hi);
+      }
+      for (int q = part; q < nent; q += kPer) {
+        const uint32_t k = ek[q];
+        cb += k < lo;
+        clo += k == lo;
+        csn += (k > lo && k < hi);
+      }
+      atomicAdd(&s_lane[lane][0], cb);
+      atomicAdd(&s_lane[lane][1], clo);
+      atomicAdd(&s_lane[lane][2], csn);
+    }
+  }
   __syncthreads();
   const int nedge = s_nedge;
 
@@ -252,21 +320,7 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
     const int j0 = lane * sb, j1 = min(nb, j0 + sb);
     if (j0 < j1) {
       const int64_t ia = i0 + j0;
-      // counts for window ia: window i0 minus what left, plus what entered
-      int cb = s_cb, clo = s_clo, csn = s_cs;
-      const int nleft = (int)(ws(ia) - l0), nent = (int)(we(ia) - e0);
-      for (int q = 0; q < nleft; ++q) {
-        const uint32_t k = lk[q];
-        cb -= k < lo;
-        clo -= k == lo;
-        csn -= (k > lo && k < hi);
-      }
-      for (int q = 0; q < nent; ++q) {
-        const uint32_t k = ek[q];
-        cb += k < lo;
-        clo += k == lo;
-        csn += (k > lo && k < hi);
-      }
+      int cb = s_cb + s_lane[lane][0], clo = s_clo + s_lane[lane][1], csn = s_cs + s_lane[lane][2];
       int64_t s = ws(ia), e = we(ia);
       auto member = [&](int pos) {
         const int64_t idx = us + (int64_t)(uint32_t)cand[pos];
