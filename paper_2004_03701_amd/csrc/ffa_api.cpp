@@ -112,6 +112,7 @@ struct Job {
   Tiling tiling;            // tiling the tables were built for
   int32_t max_counters = 0;
   DevBuf series, oct, xf, scales, tiles, need, src_rows;
+  DevBuf blk;  // series of each downsampling block (batches of more than one series)
   int32_t stats_blocks = 0;
   // Series de-reddened first (Sec. 5.2): the running median of series `index`
   // goes to element `off` of the de-reddened buffer, which the series table
@@ -136,6 +137,7 @@ struct HostTables {
   std::vector<float> scales;
   std::vector<TileDesc> tiles;
   std::vector<int32_t> src_rows, need;
+  std::vector<int32_t> blk;
 };
 
 // Device addresses of a job's tables (in the job's own buffers, or in a
@@ -148,6 +150,7 @@ struct JobTables {
   const TileDesc* tiles = nullptr;
   const int32_t* src_rows = nullptr;
   const int32_t* need = nullptr;
+  const int32_t* blk = nullptr;  // null: one series
   void* dered = nullptr;  // de-reddened series (storage type)
 };
 
@@ -344,9 +347,14 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     sd[i].halo = (int32_t)(pl.ds_fx_max >> 32) + 2;
     sd[i].block = downsample_block_samples(sd[i].halo);
     sd[i].pad = 0;
+    if (sd[i].block <= 0)
+      return fail(ctx, FFA_ERR_INVALID_ARG,
+                  "downsampling factor too large for a downsampling block (period_max / bins_min)");
     job->ds_lds_floats = std::max<int32_t>(job->ds_lds_floats, downsample_lds_floats(sd[i].block, sd[i].halo));
     if (a.normalise) job->any_normalise = true;
-    chunk += (nsamp[i] + sd[i].block - 1) / sd[i].block;
+    const int64_t nblk = (nsamp[i] + sd[i].block - 1) / sd[i].block;
+    chunk += nblk;
+    if (nseries > 1) ht->blk.insert(ht->blk.end(), (size_t)nblk, i);
     for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
     // a series that fits a group stays in one; a larger one is split
     if ((size_t)(gcells + pl.cells) > budget_cells && gcells > 0) {
@@ -483,6 +491,7 @@ ffa_status upload_job(ffa_ctx* ctx, Job* job, HostTables& ht) {
   HIP_TRY(ctx, upload(job->tiles, ht.tiles), "upload tile table");
   HIP_TRY(ctx, upload(job->src_rows, ht.src_rows), "upload source-row table");
   HIP_TRY(ctx, upload(job->need, ht.need), "upload dependency table");
+  if (!ht.blk.empty()) HIP_TRY(ctx, upload(job->blk, ht.blk), "upload block table");
   return FFA_OK;
 }
 
@@ -495,6 +504,7 @@ JobTables job_tables(const Job& job) {
   t.tiles = job.tiles.as<TileDesc>();
   t.src_rows = job.src_rows.as<int32_t>();
   t.need = job.need.as<int32_t>();
+  t.blk = job.nseries > 1 ? job.blk.as<int32_t>() : nullptr;
   t.dered = job.dered.ptr;
   return t;
 }
@@ -598,7 +608,7 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
   TimedScope ts(ctx, 1, stream, timed);
   // the downsampled series are stored in the input's type (BF16 and FP16
   // storage halve the fold's input reads); the fold converts them on load
-  HIP_TRY(ctx, launch_downsample(sd, job.nseries, tb.oct, ws.norm, job.dtype, ws.ds, job.dtype,
+  HIP_TRY(ctx, launch_downsample(sd, tb.blk, tb.oct, ws.norm, job.dtype, ws.ds, job.dtype,
                                  job.ds_blocks, job.ds_lds_floats, stream),
           "downsample kernel");
   }
@@ -1253,6 +1263,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t halo = (int32_t)(ds_fx >> 32) + 2;
   const int32_t bs = downsample_block_samples(halo);
+  if (bs <= 0) return fail(ctx, FFA_ERR_INVALID_ARG, "downsampling factor too large");
   SeriesDev sd{series, nsamp, 0, 0, 1, stats_dev ? 1 : 0, halo, bs, 0};
   OctaveDev od{ds_fx, nout, 0};
   DevBuf t1, t2;
@@ -1264,7 +1275,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   if (stats_dev)
     HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
   const int64_t nblocks = (nsamp + bs - 1) / bs;
-  HIP_TRY(ctx, launch_downsample(t1.as<SeriesDev>(), 1, t2.as<OctaveDev>(), ctx->norm.as<float>(),
+  HIP_TRY(ctx, launch_downsample(t1.as<SeriesDev>(), nullptr, t2.as<OctaveDev>(), ctx->norm.as<float>(),
                                  dtype, out_dev, dtype, nblocks, downsample_lds_floats(bs, halo), st),
           "downsample kernel");
   HIP_TRY(ctx, hipStreamSynchronize(st), "synchronise");

@@ -13,6 +13,7 @@
 // (the merges and the boxcar widths).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include <type_traits>
@@ -44,6 +45,7 @@ template <class T>
 using gptr = const __attribute__((address_space(1))) T*;
 template <class T>
 using gptr_w = __attribute__((address_space(1))) T*;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte load
 
 template <int DT>
 __device__ __forceinline__ float load_g(const void* base, int64_t i) {
@@ -299,15 +301,23 @@ __global__ void k_norm_from_stats(const double* stats, float* norm) {
 // ---------------------------------------------------------------------------
 // Downsampling (Sec. 5.3, App. A.4). Output j of octave k integrates the
 // normalised series over [j ds, (j+1) ds), ds = ds_fx / 2^32, each input
-// sample weighted by its overlap with the window. A block stages a stretch
-// of the raw series in LDS once, turns it in place into its exclusive prefix
-// sum P, and emits every output of every octave whose window starts in it:
+// sample weighted by its overlap with the window. A block owns `block` input
+// samples and emits every output of every octave whose window starts among
+// them; it reads those samples plus a halo that the last windows reach into
+// and keeps only their exclusive prefix sum P in LDS:
 //   y = (1 - fa) x[ia] + (P[ib] - P[ia + 1]) + fb x[ib],  x[i] = P[i + 1] - P[i]
-// with a = ia + fa and b = ib + fb the window edges. Only P is kept (half the
-// LDS of keeping x too, so four blocks fit a CU).
+// with a = ia + fa and b = ib + fb the window edges.
+//
+// The samples of a block are read in rounds of kDsRound: each thread takes 16
+// consecutive samples with 16-byte loads, sums them in registers, and one
+// block scan of the thread sums places every P; the raw samples never pass
+// through LDS. The prefix restarts at every block, which bounds its
+// magnitude and with it the FP32 rounding of P.
 // ---------------------------------------------------------------------------
 
 constexpr int kDsThreads = 512;
+constexpr int kDsPerThread = 16;                     // samples a thread holds per round
+constexpr int kDsRound = kDsThreads * kDsPerThread;  // samples per round
 
 // Smallest j with j * ds_fx >= x_fx (all in 2^-32 samples): a double-precision
 // estimate, then exact integer fix-ups.
@@ -320,62 +330,69 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 }
 
 constexpr int kDsMaxOctaves = 128;
-constexpr int kDsLoadIters = 24;  // samples a thread loads before storing (block + halo <= 24 * 512)
-constexpr int kDsSegMax = kDsLoadIters + 1;  // longest prefix segment of a thread (odd)
 
+// The 16 samples [q, q + 16) of a block stretch (relative to the stretch
+// start `base`, len samples), minus the mean; samples past len read as 0.
+template <int DT>
+__device__ __forceinline__ void ds_load16(const void* base, int q, int len, bool vec, float mean,
+                                          float (&v)[kDsPerThread]) {
+  if (vec && q + kDsPerThread <= len) {
+    constexpr int kLoads = DT == FFA_F32 ? 4 : 2;  // 16-byte loads
+    gptr<u32x4> src = (gptr<u32x4>)base + (int64_t)q / (DT == FFA_F32 ? 4 : 8);
+    u32x4 w[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) w[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (DT == FFA_F32) {
+          v[4 * k + e] = __uint_as_float(w[k][e]) - mean;
+        } else {
+          v[8 * k + 2 * e] = bits_value<DT>(w[k][e] & 0xffffu) - mean;
+          v[8 * k + 2 * e + 1] = bits_value<DT>(w[k][e] >> 16) - mean;
+        }
+      }
+    return;
+  }
+  // unaligned series or the ragged end: one load per sample, every load
+  // issued (clamped) before any is used
+  uint32_t b[kDsPerThread];
+#pragma unroll
+  for (int k = 0; k < kDsPerThread; ++k) b[k] = load_bits<DT>(base, min(q + k, len - 1));
+#pragma unroll
+  for (int k = 0; k < kDsPerThread; ++k) v[k] = q + k < len ? bits_value<DT>(b[k]) - mean : 0.0f;
+}
 
 template <int DT, int DO>
 __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* series,
-                                                           int32_t nseries,
+                                                           const int32_t* block_series,
                                                            const OctaveDev* oct,
                                                            const float* norm, void* out) {
-  extern __shared__ float sm[];
-  __shared__ int s_series;
-  __shared__ float s_part[kDsThreads / 64];
+  extern __shared__ __align__(16) float ps[];  // P[0 .. rounds * kDsRound]
+  __shared__ float s_part[2][kDsThreads / 64];
   __shared__ int64_t s_j0[kDsMaxOctaves];
   __shared__ uint64_t s_dsfx[kDsMaxOctaves];
   __shared__ int64_t s_off[kDsMaxOctaves];
   __shared__ int s_cum[kDsMaxOctaves + 1];
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
-  if (tid == 0) {
-    int lo = 0, hi = nseries - 1;  // last series with chunk0 <= blockIdx.x
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (series[mid].chunk0 <= (int64_t)blockIdx.x)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    s_series = lo;
-  }
-  __syncthreads();
-  const int si = s_series;
+  const int si = block_series ? block_series[blockIdx.x] : 0;
   const SeriesDev sd = series[si];
   const int64_t c0 = ((int64_t)blockIdx.x - sd.chunk0) * sd.block;
   if (c0 >= sd.nsamp) return;
   const int64_t c1 = min(c0 + (int64_t)sd.block, sd.nsamp);
   const int64_t cend = min(sd.nsamp, c1 + (int64_t)sd.halo);
   const int len = (int)(cend - c0);
-  float* ps = sm;  // len samples, then in place their len + 1 exclusive prefix sums
+  const int rounds = (len + kDsRound - 1) / kDsRound;
   const float mean = sd.normalise ? norm[2 * si] : 0.0f;
   const float inv = sd.normalise ? norm[2 * si + 1] : 1.0f;
-  // every load of a thread is in flight before its first LDS store
-  for (int q0 = 0; q0 < len; q0 += kDsLoadIters * kDsThreads) {
-    uint32_t v[kDsLoadIters];
-#pragma unroll
-    for (int k = 0; k < kDsLoadIters; ++k) {
-      // unconditional (clamped) loads: no branch for the compiler to sink
-      // the conversions into
-      const int q = min(q0 + tid + k * kDsThreads, len - 1);
-      v[k] = load_bits<DT>(sd.ptr, c0 + q);
-    }
-#pragma unroll
-    for (int k = 0; k < kDsLoadIters; ++k) {
-      const int q = q0 + tid + k * kDsThreads;
-      if (q < len) ps[q] = bits_value<DT>(v[k]) - mean;
-    }
-  }
+  const int esize = DT == FFA_F32 ? 4 : 2;
+  const void* base = static_cast<const unsigned char*>(sd.ptr) + c0 * esize;
+  // block starts are multiples of 8 samples: the 16-byte loads line up when
+  // the series itself starts on a 16-byte boundary
+  const bool vec = (reinterpret_cast<uintptr_t>(sd.ptr) & 15) == 0;
+
   // window ranges of every octave, one octave per thread: outputs whose
   // window starts in [c0, c1) are j in [ceil(c0 / ds), ceil(c1 / ds))
   const uint64_t lo_fx = (uint64_t)c0 << 32, hi_fx = (uint64_t)c1 << 32;
@@ -392,68 +409,61 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     s_off[tid] = o.off;
     s_cum[tid + 1] = j1 > j0 ? (int)(j1 - j0) : 0;  // counts, scanned below
   }
-  __syncthreads();
-  if (wave == 0) {
-    int carry = 0;
-    for (int b = 0; b < noct; b += 64) {
-      const int k = b + lane;
-      const int c = k < noct ? s_cum[k + 1] : 0;
-      const int incl = wave_inclusive_sum(c, lane);
-      wave_lds_sync();
-      if (k < noct) s_cum[k + 1] = carry + incl;
-      carry += __shfl(incl, 63, 64);
-    }
-    if (lane == 0) s_cum[0] = 0;
-  }
-  __syncthreads();
-  // exclusive prefix, in place: each thread holds a contiguous segment of an
-  // odd length (the lanes' reads fall in distinct banks) in registers, then a
-  // block scan of the segment sums
-  const int seg = ((len + kDsThreads - 1) / kDsThreads) | 1;
-  const int q0 = min(tid * seg, len), q1 = min(q0 + seg, len);
-  const bool in_regs = seg <= kDsSegMax;  // the same in every thread
-  float xv[kDsSegMax];
-  float run = 0.0f;
-  if (in_regs) {
+
+  // exclusive prefix sums of the stretch, a round at a time
+  float carry = 0.0f;  // sum of the earlier rounds
+  for (int r = 0; r < rounds; ++r) {
+    const int q = r * kDsRound + tid * kDsPerThread;
+    float v[kDsPerThread];
+    ds_load16<DT>(base, q, len, vec, mean, v);
+    float run = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kDsSegMax; ++k) {
-      xv[k] = q0 + k < q1 ? ps[q0 + k] : 0.0f;
-      run += xv[k];
+    for (int k = 0; k < kDsPerThread; ++k) {  // v becomes the inclusive prefix
+      run += v[k];
+      v[k] = run;
     }
-  } else {  // long blocks (very large factors): two passes over LDS
-    for (int q = q0; q < q1; ++q) run += ps[q];
-  }
-  float incl = wave_scan_dpp_f32(run);
-  if (lane == 63) s_part[wave] = incl;
-  __syncthreads();
-  float woff = 0.0f;
-  for (int w = 0; w < wave; ++w) woff += s_part[w];
-  float acc = woff + incl - run;
-  if (in_regs) {
+    const float incl = wave_scan_dpp_f32(run);
+    if (lane == 63) s_part[r & 1][wave] = incl;
+    __syncthreads();
+    if (r == 0 && wave == 0) {  // output counts of the octaves -> offsets
+      int cum = 0;
+      for (int b = 0; b < noct; b += 64) {
+        const int k = b + lane;
+        const int c = k < noct ? s_cum[k + 1] : 0;
+        const int ci = wave_inclusive_sum(c, lane);
+        wave_lds_sync();
+        if (k < noct) s_cum[k + 1] = cum + ci;
+        cum += __shfl(ci, 63, 64);
+      }
+      if (lane == 0) s_cum[0] = 0;
+    }
+    float woff = 0.0f, total = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kDsSegMax; ++k) {
-      if (q0 + k < q1) ps[q0 + k] = acc;
-      acc += xv[k];
+    for (int w = 0; w < kDsThreads / 64; ++w) {
+      const float pw = s_part[r & 1][w];
+      if (w < wave) woff += pw;
+      total += pw;
     }
-  } else {
-    for (int q = q0; q < q1; ++q) {  // each thread rewrites only its own segment
-      const float x = ps[q];
-      ps[q] = acc;
-      acc += x;
-    }
+    const float p0 = carry + woff + (incl - run);  // P at the thread's first sample
+    float4* dst = reinterpret_cast<float4*>(ps + q);
+#pragma unroll
+    for (int k = 0; k < kDsPerThread / 4; ++k)
+      dst[k] = make_float4(p0 + (k ? v[4 * k - 1] : 0.0f), p0 + v[4 * k], p0 + v[4 * k + 1],
+                           p0 + v[4 * k + 2]);
+    if (r == rounds - 1 && tid == kDsThreads - 1) ps[q + kDsPerThread] = p0 + run;
+    carry += total;
   }
-  if (q1 == len && q0 < q1) ps[len] = acc;
-  if (len == 0 && tid == 0) ps[0] = 0.0f;
   __syncthreads();
+
   // all outputs of all octaves, flattened; the 64 outputs of a wave step
   // share one search for their first octave, then each lane moves on past
   // the octaves that end before its output
-  const int total = s_cum[noct];
+  const int total_out = s_cum[noct];
   int lo = 0;  // octave of the wave's first output; only moves forward
-  for (int u0 = wave * 64; u0 < total; u0 += kDsThreads) {
+  for (int u0 = wave * 64; u0 < total_out; u0 += kDsThreads) {
     while (s_cum[lo + 1] <= u0) ++lo;
     const int u = u0 + lane;
-    if (u >= total) continue;
+    if (u >= total_out) continue;
     int k = lo;
     while (s_cum[k + 1] <= u) ++k;
     const uint64_t dsfx = s_dsfx[k];
@@ -1877,44 +1887,55 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
   return hipGetLastError();
 }
 
-int32_t downsample_lds_floats(int32_t block, int32_t halo) { return block + halo + 2; }
+constexpr int kDsMaxRounds = 4;  // LDS of a block: kDsMaxRounds * kDsRound floats at most
 
-int32_t downsample_block_samples(int32_t max_halo) {
-  int32_t b = 8192;
-  while (b < 4 * max_halo) b *= 2;
-  return b;
+int32_t downsample_lds_floats(int32_t block, int32_t halo) {
+  const int32_t rounds = (block + halo + kDsRound - 1) / kDsRound;
+  return rounds * kDsRound + 4;
+}
+
+int32_t downsample_block_samples(int32_t halo) {
+  // a block and its halo fill whole rounds; the block is at least four halos
+  // long (at most a fifth of the loads repeat) where LDS allows, and a
+  // multiple of 8 samples, so that 16-byte loads stay aligned
+  const int32_t pad = (halo + 7) & ~7;
+  const int32_t rounds = std::min(kDsMaxRounds, std::max(1, (5 * pad + kDsRound - 1) / kDsRound));
+  const int32_t block = rounds * kDsRound - pad;
+  return block >= pad ? block : 0;
 }
 
 template <int DT, int DO>
-hipError_t launch_downsample_t(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
-                               const float* norm, void* out, int64_t nblocks, size_t lds,
-                               hipStream_t stream) {
+hipError_t launch_downsample_t(const SeriesDev* series_dev, const int32_t* block_series,
+                               const OctaveDev* oct, const float* norm, void* out, int64_t nblocks,
+                               size_t lds, hipStream_t stream) {
   static bool done[kMaxDevices] = {};
   hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_downsample<DT, DO>),
                                     kLdsBytes - 4096, done);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_downsample<DT, DO>), dim3((unsigned)nblocks), dim3(kDsThreads), lds,
-                     stream, series_dev, nseries, oct, norm, out);
+                     stream, series_dev, block_series, oct, norm, out);
   return hipGetLastError();
 }
 
 // Output in the input's type, or FP32 from any input.
-hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
-                             const float* norm, int32_t dtype, void* out, int32_t out_dtype,
-                             int64_t nblocks, int32_t lds_floats, hipStream_t stream) {
+hipError_t launch_downsample(const SeriesDev* series_dev, const int32_t* block_series,
+                             const OctaveDev* oct, const float* norm, int32_t dtype, void* out,
+                             int32_t out_dtype, int64_t nblocks, int32_t lds_floats,
+                             hipStream_t stream) {
   const size_t lds = (size_t)lds_floats * sizeof(float);
   if (lds > (size_t)(kLdsBytes - 4096) || (out_dtype != dtype && out_dtype != FFA_F32))
     return hipErrorInvalidValue;
   const auto* s = series_dev;
+  const auto* b = block_series;
   if (dtype == FFA_BF16)
     return out_dtype == FFA_F32
-               ? launch_downsample_t<FFA_BF16, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream)
-               : launch_downsample_t<FFA_BF16, FFA_BF16>(s, nseries, oct, norm, out, nblocks, lds, stream);
+               ? launch_downsample_t<FFA_BF16, FFA_F32>(s, b, oct, norm, out, nblocks, lds, stream)
+               : launch_downsample_t<FFA_BF16, FFA_BF16>(s, b, oct, norm, out, nblocks, lds, stream);
   if (dtype == FFA_F16)
     return out_dtype == FFA_F32
-               ? launch_downsample_t<FFA_F16, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream)
-               : launch_downsample_t<FFA_F16, FFA_F16>(s, nseries, oct, norm, out, nblocks, lds, stream);
-  return launch_downsample_t<FFA_F32, FFA_F32>(s, nseries, oct, norm, out, nblocks, lds, stream);
+               ? launch_downsample_t<FFA_F16, FFA_F32>(s, b, oct, norm, out, nblocks, lds, stream)
+               : launch_downsample_t<FFA_F16, FFA_F16>(s, b, oct, norm, out, nblocks, lds, stream);
+  return launch_downsample_t<FFA_F32, FFA_F32>(s, b, oct, norm, out, nblocks, lds, stream);
 }
 
 int32_t pass_lds_bytes(int32_t rows_cap, int32_t max_p) {

@@ -40,14 +40,18 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
 
 // All pseudo-octaves of every series in one pass over the raw samples
 // (Sec. 5.3, App. A.4). nblocks = total downsampling blocks of the launch.
-// Every series is cut into blocks of its own `block` samples; lds_floats is
-// the largest downsample_lds_floats(block, halo) of the launch.
-hipError_t launch_downsample(const SeriesDev* series_dev, int32_t nseries, const OctaveDev* oct,
-                             const float* norm, int32_t dtype, void* out, int32_t out_dtype,
-                             int64_t nblocks, int32_t lds_floats, hipStream_t stream);
+// Every series is cut into blocks of its own `block` samples; block_series
+// (DEVICE, nblocks entries) names the series of each block, or is null when
+// there is one series; lds_floats is the largest
+// downsample_lds_floats(block, halo) of the launch.
+hipError_t launch_downsample(const SeriesDev* series_dev, const int32_t* block_series,
+                             const OctaveDev* oct, const float* norm, int32_t dtype, void* out,
+                             int32_t out_dtype, int64_t nblocks, int32_t lds_floats,
+                             hipStream_t stream);
 
-// Downsampling block length for a given largest halo.
-int32_t downsample_block_samples(int32_t max_halo);
+// Downsampling block length of a series whose windows reach `halo` samples
+// past a block; 0 when the halo is too long for a block's LDS.
+int32_t downsample_block_samples(int32_t halo);
 
 // LDS floats a downsampling block of `block` samples and `halo` extra uses.
 int32_t downsample_lds_floats(int32_t block, int32_t halo);

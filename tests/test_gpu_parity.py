@@ -101,6 +101,34 @@ def test_series_stats(ctx):
     assert abs(st[1] - sd) < 1e-11 * sd
 
 
+def check_downsampled(y, xn, ds_fx, ref, out_ulp):
+    """Downsampled output against the oracle, to a bound taken from the FP32
+    arithmetic of the prefix-sum method.
+
+    A block keeps the exclusive prefix sum P of its stretch (at most 32768
+    samples) in FP32; every P carries at most ~40 roundings, each no larger than
+    half an ulp of the largest |P| of the block, and an output combines four P
+    values with weights of at most 2. |P| is bounded by the range of the
+    series' cumulative sum within 32768 samples either side of the window.
+    Element by element the error stays within that worst case; its RMS must
+    stay near the few roundings of a typical P, which the bound exceeds
+    fifty-fold, so an accumulation without the per-block restart would fail.
+    The output is then rounded to its storage type (out_ulp: half an ulp,
+    relative).
+    """
+    from scipy.ndimage import maximum_filter1d, minimum_filter1d
+    span = 32768
+    cs = np.concatenate([[0.0], np.cumsum(xn)])
+    rng = maximum_filter1d(cs, 2 * span + 1) - minimum_filter1d(cs, 2 * span + 1)
+    start = (np.arange(len(ref), dtype=np.float64) * (ds_fx / 2.0 ** 32)).astype(np.int64)
+    prange = rng[np.minimum(start, len(cs) - 1)]
+    err = np.abs(y - ref)
+    worst = 256 * 2.0 ** -24 * prange + out_ulp * np.abs(ref) + 1e-7
+    assert np.all(err <= worst), (err - worst).max()
+    rms_allow = 5 * 2.0 ** -24 * np.sqrt(np.mean(prange ** 2)) + out_ulp * np.sqrt(np.mean(ref ** 2))
+    assert np.sqrt(np.mean(err ** 2)) <= rms_allow
+
+
 @pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3, 5000.3])
 def test_downsample(ctx, ds):
     n = 300_001
@@ -111,9 +139,39 @@ def test_downsample(ctx, ds):
     st = ffa.ffa_series_stats(ctx, xd)
     y = ffa.ffa_downsample(ctx, xd, ds_fx, nout, stats=st).cpu().numpy().astype(np.float64)
     mu, sd = oracle.normalise_stats(x)
-    ref = oracle.downsample((x.astype(np.float64) - mu) / sd, ds_fx, nout)
-    # FP32 prefix over a block of <= 16K samples: error ~1e-5 absolute
-    assert np.abs(y - ref).max() < 2e-5 * max(1.0, math.sqrt(ds)) * 4
+    xn = (x.astype(np.float64) - mu) / sd
+    check_downsampled(y, xn, ds_fx, oracle.downsample(xn, ds_fx, nout), 0.0)
+
+
+@pytest.mark.parametrize("tdt,dt", [(torch.float32, ffa.FFA_F32), (torch.bfloat16, ffa.FFA_BF16),
+                                     (torch.float16, ffa.FFA_F16)])
+@pytest.mark.parametrize("offset", [0, 1, 3])
+@pytest.mark.parametrize("ds", [1.0, 2.7, 651.04, 5000.3])
+def test_downsample_storage_types_and_alignment(ctx, tdt, dt, offset, ds):
+    # 16-byte loads take aligned series; a series that starts off a 16-byte
+    # boundary (offset > 0), or a ragged end, loads per sample
+    n = 200_003
+    base = torch.from_numpy(np.random.default_rng(9).standard_normal(n + offset).astype(np.float32))
+    xs = base.to(tdt)
+    x = xs.float().numpy()[offset:].astype(np.float64)
+    xd = xs.cuda()[offset:]
+    ds_fx = int(math.floor(ds * 2 ** 32 + 0.5))
+    nout = (n << 32) // ds_fx
+    st = ffa.ffa_series_stats(ctx, xd, dtype=dt)
+    y = ffa.ffa_downsample(ctx, xd, ds_fx, nout, stats=st, dtype=dt).float().cpu().numpy()
+    mu, sd = oracle.normalise_stats(x)
+    xn = (x - mu) / sd
+    ulp = {torch.float32: 0.0, torch.bfloat16: 2.0 ** -8, torch.float16: 2.0 ** -11}[tdt]
+    check_downsampled(y.astype(np.float64), xn, ds_fx, oracle.downsample(xn, ds_fx, nout), ulp)
+
+
+def test_downsample_factor_beyond_block_is_refused(ctx):
+    # a window longer than a downsampling block can hold is an argument error
+    n = 100_000
+    xd = dev(np.random.default_rng(2).standard_normal(n).astype(np.float32))
+    ds_fx = 20_000 << 32
+    with pytest.raises(RuntimeError):
+        ffa.ffa_downsample(ctx, xd, ds_fx, n // 20_000)
 
 
 # ---------------------------------------------------------------------------
