@@ -103,6 +103,7 @@ struct Job {
   int32_t ds_lds_floats = 0;
   int64_t ds_blocks = 0;
   int64_t ds_total = 0;     // elements of the downsampled buffer
+  int64_t ds_samples = 0;   // downsampled samples (the buffer less its padding)
   int64_t scr_cells = 0;    // floats per scratch buffer
   int64_t rows = 0;         // periodogram rows
   int64_t cells = 0;        // sum of m * p
@@ -385,6 +386,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
       xf.push_back(x);
     }
     ds_off += pl.ds_total;
+    job->ds_samples += pl.ds_samples;
     job->rows += pl.rows;
     job->cells += pl.cells;
     job->input_samples += nsamp[i];
@@ -587,7 +589,7 @@ ffa_status enqueue_work(ffa_ctx* ctx, const Job& job, const JobTables& tb, const
     ctx->times.profiles += job.rows;
     ctx->times.folded_cells += job.cells;
     ctx->times.input_samples += job.input_samples;
-    ctx->times.downsampled_samples += job.ds_total;
+    ctx->times.downsampled_samples += job.ds_samples;
   }
   const SeriesDev* sd = tb.series;
   for (const Job::Median& m : job.medians) {

@@ -90,23 +90,47 @@ __device__ __forceinline__ float bits_value(uint32_t b) {
   return static_cast<float>(h);
 }
 
-__device__ __forceinline__ void store_sample(void* base, int dtype, int64_t i, float v) {
-  if (dtype == FFA_F32) {
-    static_cast<float*>(base)[i] = v;
-  } else if (dtype == FFA_BF16) {
-    uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u)
-      r = static_cast<uint16_t>((u >> 16) | 0x40u);  // quiet NaN
-    else
-      r = static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // nearest even
-    static_cast<uint16_t*>(base)[i] = r;
-  } else {
-    _Float16 h = static_cast<_Float16>(v);
-    uint16_t r;
+// The 16 bits of v in a 16-bit storage type, rounded to nearest even (the
+// hardware conversions).
+template <int DT>
+__device__ __forceinline__ uint32_t half_bits(float v) {
+  uint16_t r;
+  if (DT == FFA_BF16) {
+    const __bf16 h = static_cast<__bf16>(v);
     __builtin_memcpy(&r, &h, 2);
-    static_cast<uint16_t*>(base)[i] = r;
+  } else {
+    const _Float16 h = static_cast<_Float16>(v);
+    __builtin_memcpy(&r, &h, 2);
   }
+  return r;
+}
+
+// Two values in a 16-bit storage type, lo in the low half: one packed
+// conversion.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+template <int DT>
+__device__ __forceinline__ uint32_t pack_half2(float lo, float hi) {
+  const f32x2 v = {lo, hi};
+  uint32_t r;
+  if (DT == FFA_BF16) {
+    const bf16x2 h = __builtin_convertvector(v, bf16x2);
+    __builtin_memcpy(&r, &h, 4);
+  } else {
+    const f16x2 h = __builtin_convertvector(v, f16x2);
+    __builtin_memcpy(&r, &h, 4);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void store_sample(void* base, int dtype, int64_t i, float v) {
+  if (dtype == FFA_F32)
+    static_cast<float*>(base)[i] = v;
+  else if (dtype == FFA_BF16)
+    static_cast<uint16_t*>(base)[i] = (uint16_t)half_bits<FFA_BF16>(v);
+  else
+    static_cast<uint16_t*>(base)[i] = (uint16_t)half_bits<FFA_F16>(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,6 +354,7 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 }
 
 constexpr int kDsMaxOctaves = 128;
+constexpr int kDsGroup = 8;  // consecutive outputs of one octave a thread emits together
 
 // The 16 samples [q, q + 16) of a block stretch (relative to the stretch
 // start `base`, len samples), minus the mean; samples past len read as 0.
@@ -369,9 +394,9 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
                                                            const int32_t* block_series,
                                                            const OctaveDev* oct,
                                                            const float* norm, void* out) {
-  extern __shared__ __align__(16) float ps[];  // P[0 .. rounds * kDsRound]
+  extern __shared__ __align__(16) float ps[];  // P[0 .. rounds * kDsRound + 1]
   __shared__ float s_part[2][kDsThreads / 64];
-  __shared__ int64_t s_j0[kDsMaxOctaves];
+  __shared__ int64_t s_j0[kDsMaxOctaves], s_j1[kDsMaxOctaves];
   __shared__ uint64_t s_dsfx[kDsMaxOctaves];
   __shared__ int64_t s_off[kDsMaxOctaves];
   __shared__ int s_cum[kDsMaxOctaves + 1];
@@ -394,7 +419,10 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   const bool vec = (reinterpret_cast<uintptr_t>(sd.ptr) & 15) == 0;
 
   // window ranges of every octave, one octave per thread: outputs whose
-  // window starts in [c0, c1) are j in [ceil(c0 / ds), ceil(c1 / ds))
+  // window starts in [c0, c1) are j in [ceil(c0 / ds), ceil(c1 / ds)). They
+  // are emitted in groups of kDsGroup consecutive outputs, the groups aligned
+  // to multiples of kDsGroup in j (octaves start on such multiples in the
+  // output buffer too).
   const uint64_t lo_fx = (uint64_t)c0 << 32, hi_fx = (uint64_t)c1 << 32;
   const int noct = min(sd.noct, kDsMaxOctaves);
   if (tid < noct) {
@@ -405,9 +433,11 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
       j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
     }
     s_j0[tid] = j0;
+    s_j1[tid] = j1;
     s_dsfx[tid] = o.ds_fx;
     s_off[tid] = o.off;
-    s_cum[tid + 1] = j1 > j0 ? (int)(j1 - j0) : 0;  // counts, scanned below
+    // groups, scanned below
+    s_cum[tid + 1] = j1 > j0 ? (int)((j1 - 1) / kDsGroup - j0 / kDsGroup + 1) : 0;
   }
 
   // exclusive prefix sums of the stretch, a round at a time
@@ -450,32 +480,72 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     for (int k = 0; k < kDsPerThread / 4; ++k)
       dst[k] = make_float4(p0 + (k ? v[4 * k - 1] : 0.0f), p0 + v[4 * k], p0 + v[4 * k + 1],
                            p0 + v[4 * k + 2]);
-    if (r == rounds - 1 && tid == kDsThreads - 1) ps[q + kDsPerThread] = p0 + run;
+    if (r == rounds - 1 && tid == kDsThreads - 1)  // P past the end: the total, twice
+      ps[q + kDsPerThread] = ps[q + kDsPerThread + 1] = p0 + run;
     carry += total;
   }
   __syncthreads();
 
-  // all outputs of all octaves, flattened; the 64 outputs of a wave step
-  // share one search for their first octave, then each lane moves on past
-  // the octaves that end before its output
-  const int total_out = s_cum[noct];
-  int lo = 0;  // octave of the wave's first output; only moves forward
-  for (int u0 = wave * 64; u0 < total_out; u0 += kDsThreads) {
-    while (s_cum[lo + 1] <= u0) ++lo;
-    const int u = u0 + lane;
-    if (u >= total_out) continue;
-    int k = lo;
-    while (s_cum[k + 1] <= u) ++k;
+  // all output groups of all octaves, flattened; a group's octave is the
+  // last one that starts at or before it (a binary search of the scanned
+  // counts, which skips empty octaves). Neighbouring windows share an edge,
+  // so a group reads P at kDsGroup + 1 edges.
+  const int total = s_cum[noct];
+  for (int u = tid; u < total; u += kDsThreads) {
+    int k = 0;
+#pragma unroll
+    for (int step = kDsMaxOctaves / 2; step >= 1; step >>= 1)
+      if (k + step < noct && s_cum[k + step] <= u) k += step;
     const uint64_t dsfx = s_dsfx[k];
-    const int64_t j = s_j0[k] + (u - s_cum[k]);
-    const uint64_t a = (uint64_t)j * dsfx, b = a + dsfx;
-    const int ia = (int)((int64_t)(a >> 32) - c0), ib = (int)((int64_t)(b >> 32) - c0);
-    const float fa = (float)(uint32_t)a * 2.3283064365386963e-10f;
-    const float fb = (float)(uint32_t)b * 2.3283064365386963e-10f;
-    const float pa0 = ps[ia], pa1 = ps[ia + 1], pb0 = ps[ib];
-    float y = (1.0f - fa) * (pa1 - pa0) + (pb0 - pa1);
-    if ((uint32_t)b != 0u) y += fb * (ps[ib + 1] - pb0);
-    store_sample(out, DO, s_off[k] + j, y * inv);
+    const int64_t jlo = s_j0[k], jhi = s_j1[k];
+    const int64_t jg = (jlo / kDsGroup + (u - s_cum[k])) * kDsGroup;  // first output of the group
+    // edges e = 0..kDsGroup at a = (jg + e) ds; outside the block's windows
+    // (outputs of the group that belong to a neighbouring block) the reads
+    // are clamped into the stretch and their outputs dropped
+    // edges in 2^-32 samples from the stretch start; the integer part is the
+    // sample an edge falls in, the fraction how far into it
+    float p0[kDsGroup + 1], p1[kDsGroup + 1], g[kDsGroup + 1], d[kDsGroup + 1];
+    uint64_t a = (uint64_t)jg * dsfx - ((uint64_t)c0 << 32);
+#pragma unroll
+    for (int e = 0; e <= kDsGroup; ++e) {
+      const int ia = min(max((int)(a >> 32), 0), len);
+      p0[e] = ps[ia];
+      p1[e] = ps[ia + 1];  // P[len + 1] repeats P[len]
+      d[e] = p1[e] - p0[e];                                          // x of the edge sample
+      g[e] = (float)(uint32_t)a * 2.3283064365386963e-10f * d[e];  // its part left of the edge
+      a += dsfx;
+    }
+    float y[kDsGroup];
+#pragma unroll
+    for (int e = 0; e < kDsGroup; ++e) {
+      // window [a_e, a_e+1): the part of the first sample right of its edge,
+      // the whole samples between, and the part of the last sample left of
+      // its edge
+      y[e] = ((d[e] - g[e]) + (p0[e + 1] - p1[e]) + g[e + 1]) * inv;
+    }
+    const int64_t o0 = s_off[k] + jg;
+    if (jg >= jlo && jg + kDsGroup <= jhi) {
+      if (DO == FFA_F32) {
+        gptr_w<u32x4> dst = (gptr_w<u32x4>)((float*)out + o0);
+        u32x4 w0, w1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          w0[e] = __float_as_uint(y[e]);
+          w1[e] = __float_as_uint(y[4 + e]);
+        }
+        dst[0] = w0;
+        dst[1] = w1;
+      } else {
+        u32x4 w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = pack_half2<DO>(y[2 * e], y[2 * e + 1]);
+        *(gptr_w<u32x4>)((uint16_t*)out + o0) = w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < kDsGroup; ++e)
+        if (jg + e >= jlo && jg + e < jhi) store_sample(out, DO, o0 + e, y[e]);
+    }
   }
 }
 
@@ -1888,6 +1958,7 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
 }
 
 constexpr int kDsMaxRounds = 4;  // LDS of a block: kDsMaxRounds * kDsRound floats at most
+constexpr int kDsMaxLdsBytes = (kDsMaxRounds * kDsRound + 4) * (int)sizeof(float);
 
 int32_t downsample_lds_floats(int32_t block, int32_t halo) {
   const int32_t rounds = (block + halo + kDsRound - 1) / kDsRound;
@@ -1910,7 +1981,7 @@ hipError_t launch_downsample_t(const SeriesDev* series_dev, const int32_t* block
                                size_t lds, hipStream_t stream) {
   static bool done[kMaxDevices] = {};
   hipError_t e = set_lds_limit_once(reinterpret_cast<const void*>(k_downsample<DT, DO>),
-                                    kLdsBytes - 4096, done);
+                                    kDsMaxLdsBytes, done);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_downsample<DT, DO>), dim3((unsigned)nblocks), dim3(kDsThreads), lds,
                      stream, series_dev, block_series, oct, norm, out);
@@ -1923,7 +1994,7 @@ hipError_t launch_downsample(const SeriesDev* series_dev, const int32_t* block_s
                              int32_t out_dtype, int64_t nblocks, int32_t lds_floats,
                              hipStream_t stream) {
   const size_t lds = (size_t)lds_floats * sizeof(float);
-  if (lds > (size_t)(kLdsBytes - 4096) || (out_dtype != dtype && out_dtype != FFA_F32))
+  if (lds > (size_t)kDsMaxLdsBytes || (out_dtype != dtype && out_dtype != FFA_F32))
     return hipErrorInvalidValue;
   const auto* s = series_dev;
   const auto* b = block_series;
