@@ -356,7 +356,7 @@ ffa_status build_job(ffa_ctx* ctx, int32_t nseries, const void* const* series,
     const int64_t nblk = (nsamp[i] + sd[i].block - 1) / sd[i].block;
     chunk += nblk;
     if (nseries > 1) ht->blk.insert(ht->blk.end(), (size_t)nblk, i);
-    for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off});
+    for (const Octave& o : pl.oct) od.push_back(OctaveDev{o.ds_fx, o.nsamp, ds_off + o.ds_off, 1.0 / (double)o.ds_fx});
     // a series that fits a group stays in one; a larger one is split
     if ((size_t)(gcells + pl.cells) > budget_cells && gcells > 0) {
       spans.push_back(GroupSpan{gx0, xf.size(), gcells});
@@ -1267,7 +1267,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   const int32_t bs = downsample_block_samples(halo);
   if (bs <= 0) return fail(ctx, FFA_ERR_INVALID_ARG, "downsampling factor too large");
   SeriesDev sd{series, nsamp, 0, 0, 1, stats_dev ? 1 : 0, halo, bs, 0};
-  OctaveDev od{ds_fx, nout, 0};
+  OctaveDev od{ds_fx, nout, 0, 1.0 / (double)ds_fx};
   DevBuf t1, t2;
   HIP_TRY(ctx, t1.reserve(sizeof sd), "allocate");
   HIP_TRY(ctx, t2.reserve(sizeof od), "allocate");

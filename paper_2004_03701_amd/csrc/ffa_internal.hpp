@@ -38,6 +38,10 @@ constexpr int kMetaNodes = (2 << kMaxRangeLevels) - 1;
 constexpr int kMetaInts = 6 * kMetaNodes + kMaxRangeLevels + 4;
 // LDS of a CU (gfx950: 160 KiB); a workgroup of w waves uses w / 16 of it.
 constexpr int kLdsBytes = 160 * 1024;
+// Downsampled octaves start on multiples of kDsGroup samples of their buffer:
+// the downsampler emits kDsGroup consecutive outputs of an octave at a time,
+// with whole 16-byte stores.
+constexpr int kDsGroup = 8;
 inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWavesLarge * waves; }
 // LDS set aside for the S/N step; range tiles keep their pair-operation
 // records of kOpInts ints here during the merges, so a range tile has at most

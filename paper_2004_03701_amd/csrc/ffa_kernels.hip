@@ -344,9 +344,9 @@ constexpr int kDsPerThread = 16;                     // samples a thread holds p
 constexpr int kDsRound = kDsThreads * kDsPerThread;  // samples per round
 
 // Smallest j with j * ds_fx >= x_fx (all in 2^-32 samples): a double-precision
-// estimate, then exact integer fix-ups.
-__device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
-  int64_t j = (int64_t)ceil((double)x_fx / (double)ds_fx);
+// estimate (rcp = 1 / ds_fx), then exact integer fix-ups.
+__device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx, double rcp) {
+  int64_t j = (int64_t)ceil((double)x_fx * rcp);
   if (j < 0) j = 0;
   while (j > 0 && (uint64_t)(j - 1) * ds_fx >= x_fx) --j;
   while ((uint64_t)j * ds_fx < x_fx) ++j;
@@ -354,7 +354,6 @@ __device__ __forceinline__ int64_t first_window(uint64_t x_fx, uint64_t ds_fx) {
 }
 
 constexpr int kDsMaxOctaves = 128;
-constexpr int kDsGroup = 8;  // consecutive outputs of one octave a thread emits together
 
 // The 16 samples [q, q + 16) of a block stretch (relative to the stretch
 // start `base`, len samples), minus the mean; samples past len read as 0.
@@ -429,8 +428,8 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     const OctaveDev o = oct[sd.oct0 + tid];
     int64_t j0 = 0, j1 = 0;
     if (o.nsamp > 0) {
-      j0 = first_window(lo_fx, o.ds_fx);
-      j1 = min(first_window(hi_fx, o.ds_fx), o.nsamp);
+      j0 = first_window(lo_fx, o.ds_fx, o.rcp);
+      j1 = min(first_window(hi_fx, o.ds_fx, o.rcp), o.nsamp);
     }
     s_j0[tid] = j0;
     s_j1[tid] = j1;
@@ -499,47 +498,50 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     const uint64_t dsfx = s_dsfx[k];
     const int64_t jlo = s_j0[k], jhi = s_j1[k];
     const int64_t jg = (jlo / kDsGroup + (u - s_cum[k])) * kDsGroup;  // first output of the group
-    // edges e = 0..kDsGroup at a = (jg + e) ds; outside the block's windows
-    // (outputs of the group that belong to a neighbouring block) the reads
-    // are clamped into the stretch and their outputs dropped
-    // edges in 2^-32 samples from the stretch start; the integer part is the
-    // sample an edge falls in, the fraction how far into it
-    float p0[kDsGroup + 1], p1[kDsGroup + 1], g[kDsGroup + 1], d[kDsGroup + 1];
+    // edges e = 0..kDsGroup at a = (jg + e) ds, in 2^-32 samples from the
+    // stretch start: the integer part is the sample an edge falls in, the
+    // fraction how far into it. Outside the block's windows (outputs of the
+    // group that belong to a neighbouring block) the reads are clamped into
+    // the stretch and the outputs dropped.
+    float y[kDsGroup];
+    float d_prev = 0.0f, g_prev = 0.0f, p1_prev = 0.0f;
     uint64_t a = (uint64_t)jg * dsfx - ((uint64_t)c0 << 32);
 #pragma unroll
     for (int e = 0; e <= kDsGroup; ++e) {
       const int ia = min(max((int)(a >> 32), 0), len);
-      p0[e] = ps[ia];
-      p1[e] = ps[ia + 1];  // P[len + 1] repeats P[len]
-      d[e] = p1[e] - p0[e];                                          // x of the edge sample
-      g[e] = (float)(uint32_t)a * 2.3283064365386963e-10f * d[e];  // its part left of the edge
-      a += dsfx;
-    }
-    float y[kDsGroup];
-#pragma unroll
-    for (int e = 0; e < kDsGroup; ++e) {
-      // window [a_e, a_e+1): the part of the first sample right of its edge,
+      const float p0 = ps[ia];
+      const float p1 = ps[ia + 1];  // P[len + 1] repeats P[len]
+      const float d = p1 - p0;                                          // x of the edge sample
+      const float g = (float)(uint32_t)a * 2.3283064365386963e-10f * d;  // its part left of the edge
+      // window [a_e-1, a_e): the part of the first sample right of its edge,
       // the whole samples between, and the part of the last sample left of
       // its edge
-      y[e] = ((d[e] - g[e]) + (p0[e + 1] - p1[e]) + g[e + 1]) * inv;
+      if (e > 0) y[e - 1] = ((d_prev - g_prev) + (p0 - p1_prev) + g) * inv;
+      d_prev = d;
+      g_prev = g;
+      p1_prev = p1;
+      a += dsfx;
     }
     const int64_t o0 = s_off[k] + jg;
     if (jg >= jlo && jg + kDsGroup <= jhi) {
       if (DO == FFA_F32) {
         gptr_w<u32x4> dst = (gptr_w<u32x4>)((float*)out + o0);
-        u32x4 w0, w1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          w0[e] = __float_as_uint(y[e]);
-          w1[e] = __float_as_uint(y[4 + e]);
+        for (int q = 0; q < kDsGroup / 4; ++q) {
+          u32x4 w;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[e] = __float_as_uint(y[4 * q + e]);
+          dst[q] = w;
         }
-        dst[0] = w0;
-        dst[1] = w1;
       } else {
-        u32x4 w;
+        gptr_w<u32x4> dst = (gptr_w<u32x4>)((uint16_t*)out + o0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w[e] = pack_half2<DO>(y[2 * e], y[2 * e + 1]);
-        *(gptr_w<u32x4>)((uint16_t*)out + o0) = w;
+        for (int q = 0; q < kDsGroup / 8; ++q) {
+          u32x4 w;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[e] = pack_half2<DO>(y[8 * q + 2 * e], y[8 * q + 2 * e + 1]);
+          dst[q] = w;
+        }
       }
     } else {
 #pragma unroll

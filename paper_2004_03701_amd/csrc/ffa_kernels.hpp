@@ -27,6 +27,7 @@ struct OctaveDev {
   uint64_t ds_fx;
   int64_t nsamp;      // downsampled samples
   int64_t off;        // element offset in the downsampled buffer
+  double rcp;         // 1 / ds_fx: a first estimate of window indices, refined exactly
 };
 
 // Normalisation statistics of each series (Sec. 5.2), FP64:

@@ -135,9 +135,7 @@ ffa_status build_series_plan(const ffa_search_params& a, int64_t nsamp, SeriesPl
       any = true;
     }
     if (any) {
-      // octaves start on multiples of 8 samples: whole 16-byte stores of
-      // downsampled samples
-      plan.ds_total += (o.nsamp + 7) & ~int64_t(7);
+      plan.ds_total += (o.nsamp + kDsGroup - 1) / kDsGroup * kDsGroup;
       plan.ds_samples += o.nsamp;
       plan.ds_fx_max = std::max(plan.ds_fx_max, ds_fx);
     } else {

@@ -32,7 +32,7 @@ struct SeriesPlan {
   std::vector<Octave> oct;
   std::vector<Transform> tr;
   int64_t rows = 0;        // kept periodogram rows
-  int64_t ds_total = 0;    // elements of the downsampled buffer (octaves padded to 8)
+  int64_t ds_total = 0;    // elements of the downsampled buffer (octaves padded to kDsGroup)
   int64_t ds_samples = 0;  // downsampled samples of all octaves
   uint64_t ds_fx_max = 0;
   int64_t cells = 0;       // sum of m * p over transforms
