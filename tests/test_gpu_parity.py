@@ -372,6 +372,34 @@ def test_batch_equals_single_series_bit_for_bit(ctx):
     assert snr_close(snr_b[offs[2]:offs[2] + ref.snr.shape[0]], ref.snr) < SNR_RTOL
 
 
+@pytest.mark.parametrize("tdt,dt", [(torch.float32, ffa.FFA_F32), (torch.bfloat16, ffa.FFA_BF16)])
+def test_batch_with_unaligned_series(ctx, tdt, dt):
+    # series that start off a 16-byte boundary (views at odd offsets) take
+    # the per-sample loads of the statistics and the downsampler; in a batch
+    # with aligned series of other plans (other block lengths), each must
+    # equal its own single-series search bit for bit, and the oracle
+    xs, cfgs = batch_inputs(4)
+    views = []
+    for i, x in enumerate(xs):
+        off = (0, 1, 3, 0)[i]
+        buf = torch.zeros(x.size + off, dtype=tdt, device="cuda")
+        buf[off:] = torch.from_numpy(x).to(tdt)
+        views.append(buf[off:])
+    params = [ffa.make_params(t, lo, hi, 240, 259, synth.WIDTHS_DUTY, dtype=dt) for t, lo, hi in cfgs]
+    snr_b, offs = ffa.ffa_search_batch(ctx, views, params)
+    torch.cuda.synchronize()
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    snr_b = snr_b.cpu().numpy()
+    for i, v in enumerate(views):
+        _, _, s1 = ffa.ffa_search(ctx, v, params[i])
+        torch.cuda.synchronize()
+        assert np.array_equal(snr_b[offs[i]:offs[i] + s1.shape[0]], s1.cpu().numpy()), i
+    if dt == ffa.FFA_F32:
+        t, lo, hi = cfgs[1]
+        ref = oracle.search(xs[1], t, lo, hi, 240, 259, synth.WIDTHS_DUTY)
+        assert snr_close(snr_b[offs[1]:offs[1] + ref.snr.shape[0]], ref.snr) < SNR_RTOL
+
+
 def test_graph_replay_matches_eager(ctx):
     xs, cfgs = batch_inputs(4)
     dev_x = [dev(x) for x in xs]
