@@ -322,6 +322,58 @@ ffa_status ffa_find_peaks_batch(ffa_ctx* ctx, int32_t nseries, const int64_t* ns
                                 int64_t capacity_peaks, int64_t* npeaks_host, double* poly_host,
                                 void* stream);
 
+/* ------------------------------------------------------------------------
+ * Multi-DM pipeline pieces (Sec. 5.7). The search runs once per dispersion
+ * measure (DM) trial; around it the paper chooses the DM trials to search by
+ * the classical smearing rule, groups the peaks of all trials into clusters
+ * in frequency and flags clusters that are harmonics of others. The paper
+ * gives no rules for these; the ones below are this library's. All three are
+ * host computations on host arrays (lists of a few thousand entries) and need
+ * no context or GPU. Each returns FFA_ERR_INVALID_ARG (nothing written) for a
+ * null pointer, a negative count, or the conditions named.
+ * ------------------------------------------------------------------------ */
+
+/* The DM trials to search. A DM error dDM smears a pulse across the band by
+ * k_DM * dDM * (f_lo^-2 - f_hi^-2), k_DM = 4.148808e3 s MHz^2 pc^-1 cm^3;
+ * the DM step is the dDM whose half gives max_smear_s. Of the given trials,
+ * the fewest are chosen such that every given trial lies within half a step
+ * of a chosen one (greedy from the lowest DM, which is optimal on a line).
+ *   dm         HOST, n DM trials in pc cm^-3, ascending (else an error).
+ *   f_lo_mhz, f_hi_mhz  band edges, 0 < f_lo < f_hi; max_smear_s > 0.
+ *   keep       HOST, n int32: the indices of the chosen trials, ascending.
+ *   nkeep      HOST, one int32: how many were chosen. */
+ffa_status ffa_select_dm_trials(const double* dm, int32_t n, double f_lo_mhz, double f_hi_mhz,
+                                double max_smear_s, int32_t* keep, int32_t* nkeep);
+
+/* Clusters of peaks in frequency: ordered by frequency, peaks belong to one
+ * cluster while consecutive ones are at most tol_hz apart (DM and width play
+ * no part). Clusters are numbered in ascending frequency; a cluster's
+ * parameters are those of its brightest member (the lowest index among equal
+ * S/N).
+ *   freq, snr    HOST, n frequencies (Hz, finite) and S/N of the peaks.
+ *   tol_hz       >= 0 (typically the periodogram's cluster gap / T).
+ *   cluster_of   HOST, n int32: the cluster of each peak.
+ *   brightest    HOST, n int32: the brightest peak of cluster c at [c].
+ *   members      HOST, n int32: the member count of cluster c at [c].
+ *   nclusters    HOST, one int32. */
+ffa_status ffa_cluster_frequencies(const double* freq, const float* snr, int32_t n, double tol_hz,
+                                   int32_t* cluster_of, int32_t* brightest, int32_t* members,
+                                   int32_t* nclusters);
+
+/* Harmonic flags: entry j is a harmonic of entry i when i is brighter (higher
+ * S/N, or equal S/N and a lower index) and, for coprime n, m in
+ * [1, max_order] other than n = m = 1, |f_j - (n / m) f_i| <= tol_hz (1 + n/m).
+ * The parent is the brightest such i, its ratio the one of smallest n + m,
+ * then smallest n. Entries need not be sorted.
+ *   freq, snr    HOST, n frequencies (Hz, > 0, finite) and S/N (e.g. of the
+ *                clusters' brightest peaks).
+ *   tol_hz >= 0; 1 <= max_order <= 64.
+ *   parent       HOST, n int32: i, or -1 when j is no harmonic.
+ *   harm_num, harm_den  HOST, n int32: n and m (0 when no parent). */
+ffa_status ffa_flag_harmonics(const double* freq, const float* snr, int32_t n, double tol_hz,
+                              int32_t max_order, int32_t* parent, int32_t* harm_num,
+                              int32_t* harm_den);
+
 /* Per-kernel device time of the calls made while timing is on. Each launch
  * is bracketed by HIP events on the stream it runs on (not inside captured
  * graphs). */

@@ -36,7 +36,8 @@ EXPORTED = (
     "ffa_plan_export", "ffa_search", "ffa_search_batch", "ffa_transform", "ffa_series_stats",
     "ffa_downsample", "ffa_sync_status", "ffa_get_tiling", "ffa_set_tiling", "ffa_autotune",
     "ffa_set_timing", "ffa_read_timing", "ffa_find_peaks_batch", "ffa_search_ranges",
-    "ffa_search_noalloc", "ffa_running_median",
+    "ffa_search_noalloc", "ffa_running_median", "ffa_select_dm_trials", "ffa_cluster_frequencies",
+    "ffa_flag_harmonics",
 )
 
 FFA_NOALLOC_WORKSPACE_BYTES = 128 << 20
@@ -148,6 +149,10 @@ def lib() -> ctypes.CDLL:
         "ffa_search_ranges": ([vp, vp, i64, pp, i32, vp, vp, vp, vp, i64, vp], i32),
         "ffa_find_peaks_batch": ([vp, i32, P(i64), pp, P(i64), vp, i64, P(ffa_peak_params), vp,
                                   i64, P(i64), vp, vp], i32),
+        "ffa_select_dm_trials": ([vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                                  P(i32)], i32),
+        "ffa_cluster_frequencies": ([vp, vp, i32, ctypes.c_double, vp, vp, vp, P(i32)], i32),
+        "ffa_flag_harmonics": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -431,3 +436,57 @@ def ffa_find_peaks_batch(ctx, snr, params: Sequence[ffa_search_params], nsamp: S
         raise FFAError(st, f"{int(counts.sum())} peaks found, capacity {capacity}")
     _check(st, ctx)
     return out[:int(counts.sum())].copy(), counts, poly
+
+
+# ---------------------------------------------------------------------------
+# Multi-DM pipeline pieces (Sec. 5.7): host computations, no context needed.
+# ---------------------------------------------------------------------------
+
+def _host_array(v, dtype):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(v, dtype=dtype))
+
+
+def ffa_select_dm_trials(dms, f_lo_mhz: float, f_hi_mhz: float, max_smear_s: float):
+    """Indices (ascending) of the DM trials to search."""
+    import numpy as np
+    d = _host_array(dms, np.float64)
+    keep = np.empty(max(1, d.size), dtype=np.int32)
+    nk = ctypes.c_int32(0)
+    _check(lib().ffa_select_dm_trials(d.ctypes.data, d.size, float(f_lo_mhz), float(f_hi_mhz),
+                                      float(max_smear_s), keep.ctypes.data, ctypes.byref(nk)))
+    return keep[:nk.value].copy()
+
+
+def ffa_cluster_frequencies(freq, snr, tol_hz: float):
+    """(cluster of each peak, brightest peak of each cluster, member counts)."""
+    import numpy as np
+    f = _host_array(freq, np.float64)
+    s = _host_array(snr, np.float32)
+    if s.size != f.size:
+        raise ValueError("freq and snr differ in length")
+    n = f.size
+    cl = np.empty(max(1, n), dtype=np.int32)
+    br = np.empty(max(1, n), dtype=np.int32)
+    mb = np.empty(max(1, n), dtype=np.int32)
+    nc = ctypes.c_int32(0)
+    _check(lib().ffa_cluster_frequencies(f.ctypes.data, s.ctypes.data, n, float(tol_hz),
+                                         cl.ctypes.data, br.ctypes.data, mb.ctypes.data,
+                                         ctypes.byref(nc)))
+    return cl[:n].copy(), br[:nc.value].copy(), mb[:nc.value].copy()
+
+
+def ffa_flag_harmonics(freq, snr, tol_hz: float, max_order: int = 8):
+    """(parent or -1, ratio numerator, ratio denominator) of every entry."""
+    import numpy as np
+    f = _host_array(freq, np.float64)
+    s = _host_array(snr, np.float32)
+    if s.size != f.size:
+        raise ValueError("freq and snr differ in length")
+    n = f.size
+    par = np.empty(max(1, n), dtype=np.int32)
+    num = np.empty(max(1, n), dtype=np.int32)
+    den = np.empty(max(1, n), dtype=np.int32)
+    _check(lib().ffa_flag_harmonics(f.ctypes.data, s.ctypes.data, n, float(tol_hz), int(max_order),
+                                    par.ctypes.data, num.ctypes.data, den.ctypes.data))
+    return par[:n].copy(), num[:n].copy(), den[:n].copy()

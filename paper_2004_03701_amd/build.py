@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffa_mi355x.so")
 SOURCES = ["ffa_kernels.hip", "ffa_peaks.hip", "ffa_median.hip", "ffa_noalloc.hip", "ffa_plan.cpp",
-           "ffa_api.cpp"]
+           "ffa_api.cpp", "ffa_pipeline.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
