@@ -123,16 +123,19 @@ __device__ void select_two(const void* x, int64_t c0, int64_t c1, int64_t r0, in
     const uint32_t p0 = s_prefix[0], p1 = s_prefix[1];
     const uint32_t dmask = (1u << bits) - 1u;
     const int sh = shift;
+    // while both ranks share their prefix (always in the first pass) one
+    // histogram serves both
+    const bool shared = p0 == p1;
     for_each_key<DT>(x, c0, c1, [&](int64_t, uint32_t k) {
       const uint32_t d = (k >> sh) & dmask;
       if ((k & mask) == p0) atomicAdd(&hist[d], 1);
-      if ((k & mask) == p1) atomicAdd(&hist[kBins + d], 1);
+      if (!shared && (k & mask) == p1) atomicAdd(&hist[kBins + d], 1);
     });
     __syncthreads();
     // wave w < 2 finds the digit of rank w: lane l holds bins 32 l .. 32 l + 31
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (w < 2) {
-      const int* hh = hist + w * kBins;
+      const int* hh = hist + (shared ? 0 : w * kBins);
       int tot = 0;
       for (int q = 0; q < kBins / 64; ++q) tot += hh[(kBins / 64) * l + q];
       int incl = tot;
