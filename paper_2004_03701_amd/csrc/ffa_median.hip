@@ -285,32 +285,57 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
     if (threadIdx.x == 0) s_nedge = base;
   }
   // counts of each sliding lane's first window: window i0 minus the samples
-  // that left, plus those that entered, 16 threads per lane
-  for (int q = threadIdx.x; q < kMedLanes * 3; q += kMedThreads) (&s_lane[0][0])[q] = 0;
-  __syncthreads();
+  // that left, plus those that entered. The three counts of a key (below lo,
+  // equal to lo, strictly between) sit in 16-bit fields of one 64-bit word;
+  // an exclusive scan over the leaving and over the entering keys (two per
+  // thread, held per thread in the histogram's LDS, free by now) gives every
+  // lane its counts with two reads.
   {
-    constexpr int kPer = kMedThreads / kMedLanes;
-    const int lane = threadIdx.x / kPer, part = threadIdx.x % kPer;
-    const int sb = (nb + kMedLanes - 1) / kMedLanes;
-    const int64_t ia = i0 + (int64_t)lane * sb;
-    if (lane * sb < nb) {
-      const int nleft = (int)(ws(ia) - l0), nent = (int)(we(ia) - e0);
-      int cb = 0, clo = 0, csn = 0;
-      for (int q = part; q < nleft; q += kPer) {
-        const uint32_t k = lk[q];
-        cb -= k < lo;
-        clo -= k == lo;
-        csn -= (k > lo && k < hi);
+    __shared__ unsigned long long s_wtot[2][kMedThreads / 64];
+    unsigned long long* pre = reinterpret_cast<unsigned long long*>(hist);  // [2][kMedThreads]
+    auto cls = [&](uint32_t k) -> unsigned long long {
+      return k < lo ? 1ull : k == lo ? (1ull << 16) : k < hi ? (1ull << 32) : 0ull;
+    };
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    unsigned long long own[2], incl[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const uint32_t* keys = side ? ek : lk;
+      const int cnt = side ? ne : nl;
+      own[side] = (2 * t < cnt ? cls(keys[2 * t]) : 0ull) + (2 * t + 1 < cnt ? cls(keys[2 * t + 1]) : 0ull);
+      unsigned long long v = own[side];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
       }
-      for (int q = part; q < nent; q += kPer) {
-        const uint32_t k = ek[q];
-        cb += k < lo;
-        clo += k == lo;
-        csn += (k > lo && k < hi);
+      incl[side] = v;
+      if (lane == 63) s_wtot[side][wave] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      unsigned long long off = 0;
+      for (int w = 0; w < wave; ++w) off += s_wtot[side][w];
+      pre[side * kMedThreads + t] = off + incl[side] - own[side];
+    }
+    __syncthreads();
+    if (t < kMedLanes) {
+      const int sb = (nb + kMedLanes - 1) / kMedLanes;
+      const int64_t ia = i0 + (int64_t)t * sb;
+      if (t * sb < nb) {
+        auto prefix = [&](int side, int p) {  // the fields summed over keys [0, p)
+          const uint32_t* keys = side ? ek : lk;
+          unsigned long long v = pre[side * kMedThreads + p / 2];
+          if (p & 1) v += cls(keys[p - 1]);
+          return v;
+        };
+        const unsigned long long gone = prefix(0, (int)(ws(ia) - l0));
+        const unsigned long long come = prefix(1, (int)(we(ia) - e0));
+        s_lane[t][0] = (int)(come & 0xffff) - (int)(gone & 0xffff);
+        s_lane[t][1] = (int)((come >> 16) & 0xffff) - (int)((gone >> 16) & 0xffff);
+        s_lane[t][2] = (int)((come >> 32) & 0xffff) - (int)((gone >> 32) & 0xffff);
       }
-      atomicAdd(&s_lane[lane][0], cb);
-      atomicAdd(&s_lane[lane][1], clo);
-      atomicAdd(&s_lane[lane][2], csn);
     }
   }
   __syncthreads();
