@@ -16,10 +16,10 @@
 //      between them as a candidate (at most 4 B of them whatever the ties:
 //      samples equal to a bound are only counted) and sorts the candidates
 //      by (key, index) in LDS;
-//   3. lets each lane of one wave slide a sub-block of outputs: the counts
+//   3. lets each of 512 threads slide a sub-block of outputs: the counts
 //      of window samples below lo, equal to lo and strictly between the
 //      bounds change by at most two per output, and the position of the
-//      median among the sorted candidates moves by a few places; a lane's
+//      median among the sorted candidates moves by a few places; a thread's
 //      first position comes from one walk over the candidates that lie
 //      outside C (the others are in every window).
 #include <hip/hip_runtime.h>
@@ -34,7 +34,7 @@ namespace {
 constexpr int kMedThreads = 1024;
 constexpr int kMedBlockMax = 2048;          // outputs per workgroup
 constexpr int kMedCap = 4 * kMedBlockMax;   // candidates (a power of two)
-constexpr int kMedLanes = 64;               // lanes sliding the outputs
+constexpr int kMedLanes = 512;              // threads sliding the outputs, a sub-block each
 
 template <class T>
 using gptr = const __attribute__((address_space(1))) T*;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
   __syncthreads();
   const int nedge = s_nedge;
 
-  // 3. one wave slides the outputs, each lane a sub-block
+  // 3. kMedLanes threads slide the outputs, each a sub-block
   if (threadIdx.x < kMedLanes) {
     const int lane = threadIdx.x;
     const int sb = (nb + kMedLanes - 1) / kMedLanes;
