@@ -12,6 +12,9 @@
 // workgroup
 //   1. finds the two bounding values lo and hi of C by one radix selection
 //      for both on order-preserving 32-bit keys (digits of 11, 11, 10 bits);
+//      when, after the first digit, the keys between the two bounds' digits
+//      are few enough, it instead gathers them (with the union's) and finds
+//      both bounds in their sorted order, which step 2 sorts anyway;
 //   2. keeps every sample of the union of the windows whose key lies strictly
 //      between them as a candidate (at most 4 B of them whatever the ties:
 //      samples equal to a bound are only counted) and sorts the candidates
@@ -98,16 +101,30 @@ __device__ __forceinline__ void for_each_key(const void* x, int64_t a, int64_t b
 }
 
 constexpr int kDigitBits[3] = {11, 11, 10};  // digits from the top of the key
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
 constexpr int kBins = 2048;
 
 // The keys of ranks r0 and r1 (0-based) among the keys of x[c0, c1), by one
 // radix selection for both: three digit passes, each counting the keys that
 // share the prefix found so far of either rank. All threads return them.
+//
+// After the first pass it may stop early: when the keys of x[c0, c1) whose
+// top digit lies between the two ranks' digits, plus `extra` more, fit
+// kMedCap, it returns true with that key range [*range_lo, *range_hi] and
+// the count of keys below it (*below) instead of the two keys; the caller then
+// gathers the range and finds both keys by sorting it.
 template <int DT>
-__device__ void select_two(const void* x, int64_t c0, int64_t c1, int64_t r0, int64_t r1,
-                           int* hist /* 2 * kBins */, uint32_t* k0, uint32_t* k1) {
+__device__ bool select_two(const void* x, int64_t c0, int64_t c1, int64_t r0, int64_t r1,
+                           int64_t extra, int* hist /* 2 * kBins */, uint32_t* k0, uint32_t* k1,
+                           uint32_t* range_lo, uint32_t* range_hi, int64_t* below) {
   __shared__ uint32_t s_prefix[2];
   __shared__ int64_t s_rank[2];
+  __shared__ int64_t s_inrange;
   if (threadIdx.x == 0) {
     s_prefix[0] = s_prefix[1] = 0;
     s_rank[0] = r0;
@@ -158,10 +175,28 @@ __device__ void select_two(const void* x, int64_t c0, int64_t c1, int64_t r0, in
       }
     }
     __syncthreads();
+    if (pass == 0) {  // one histogram serves both ranks here
+      const uint32_t d0 = s_prefix[0] >> sh, d1 = s_prefix[1] >> sh;
+      if (threadIdx.x < 64) {
+        int64_t c = 0;
+        for (uint32_t d = d0 + threadIdx.x; d <= d1; d += 64) c += hist[d];
+        c = wave_sum64(c);
+        if (threadIdx.x == 0) s_inrange = c;
+      }
+      __syncthreads();
+      if (s_inrange + extra <= kMedCap) {
+        *range_lo = d0 << sh;
+        *range_hi = (d1 << sh) | ((1u << sh) - 1u);
+        *below = r0 - s_rank[0];
+        __syncthreads();  // every thread has read them before a later call resets them
+        return true;
+      }
+    }
   }
   *k0 = s_prefix[0];
   *k1 = s_prefix[1];
   __syncthreads();  // every thread has read them before a later call resets them
+  return false;
 }
 
 template <int DT>
@@ -206,16 +241,32 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
     if (threadIdx.x == 0) atomicOr(err, kMedErrBit);
     return;
   }
-  uint32_t lo, hi;
-  select_two<DT>(x, cs, ce, lo_rank, hi_rank, hist, &lo, &hi);
+  uint32_t lo = 0, hi = 0, range_lo = 0, range_hi = 0;
+  int64_t below = 0;
+  const bool early = select_two<DT>(x, cs, ce, lo_rank, hi_rank, (cs - us) + (ue - ce), hist, &lo,
+                                    &hi, &range_lo, &range_hi, &below);
 
-  // 2. candidates (lo < key < hi) of the union, and the counts of window i0
+  // 2. candidates (lo < key < hi) of the union, and the counts of window i0;
+  // after an early stop of the selection, every key of the union in the
+  // range that holds both bounds (sorted below, where the bounds are found)
   if (threadIdx.x == 0) {
     s_cnt = 0;
     s_cb = s_clo = s_cs = 0;
   }
   __syncthreads();
-  {
+  if (early) {
+    int cb = 0;
+    const int64_t w0 = ws(i0), w1 = we(i0);
+    for_each_key<DT>(x, us, ue, [&](int64_t i, uint32_t k) {
+      if (k < range_lo) {
+        cb += i >= w0 && i < w1;
+      } else if (k <= range_hi) {
+        const int slot = atomicAdd(&s_cnt, 1);
+        if (slot < kMedCap) cand[slot] = ((unsigned long long)k << 32) | (uint32_t)(i - us);
+      }
+    });
+    atomicAdd(&s_cb, cb);
+  } else {
     int cb = 0, clo = 0, csn = 0;
     const int64_t w0 = ws(i0), w1 = we(i0);
     for_each_key<DT>(x, us, ue, [&](int64_t i, uint32_t k) {
@@ -240,7 +291,7 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
   for (int j = threadIdx.x; j < nl; j += kMedThreads) lk[j] = key_at<DT>(x, l0 + j);
   for (int j = threadIdx.x; j < ne; j += kMedThreads) ek[j] = key_at<DT>(x, e0 + j);
   __syncthreads();
-  const int ncand = s_cnt;
+  int ncand = s_cnt;
   if (ncand > kMedCap) {  // cannot happen: at most 2 B from C and 2 B outside it
     if (threadIdx.x == 0) atomicOr(err, kMedErrBit);
     return;
@@ -264,6 +315,77 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
       }
       __syncthreads();
     }
+  }
+  if (early) {
+    // the bounds are the C members of ranks lo_rank - below and
+    // hi_rank - below in the sorted range; then the run strictly between
+    // them moves to the front, and the counts of window i0 are completed
+    constexpr int kEach = kMedCap / kMedThreads;
+    __shared__ int s_wc[kMedThreads / 64];
+    __shared__ uint32_t s_lo_key, s_hi_key;
+    __shared__ int s_pa, s_pb;
+    const int t = threadIdx.x, a0 = kEach * t, lane = t & 63, wave = t >> 6;
+    auto in_core = [&](int j) {
+      const int64_t idx = us + (int64_t)(uint32_t)cand[j];
+      return idx >= cs && idx < ce;
+    };
+    int own = 0;
+#pragma unroll
+    for (int e = 0; e < kEach; ++e) own += (a0 + e < ncand && in_core(a0 + e)) ? 1 : 0;
+    int incl = own;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += u;
+    }
+    if (lane == 63) s_wc[wave] = incl;
+    if (t == 0) s_pa = s_pb = 0;
+    __syncthreads();
+    int rank = incl - own;
+    for (int w = 0; w < wave; ++w) rank += s_wc[w];
+    const int64_t rlo = lo_rank - below, rhi = hi_rank - below;
+#pragma unroll
+    for (int e = 0; e < kEach; ++e) {
+      if (a0 + e < ncand && in_core(a0 + e)) {
+        if (rank == rlo) s_lo_key = (uint32_t)(cand[a0 + e] >> 32);
+        if (rank == rhi) s_hi_key = (uint32_t)(cand[a0 + e] >> 32);
+        ++rank;
+      }
+    }
+    __syncthreads();
+    lo = s_lo_key;
+    hi = s_hi_key;
+    int le = 0, lt = 0, cb = 0, clo = 0, csn = 0;
+    const int64_t w0 = ws(i0), w1 = we(i0);
+#pragma unroll
+    for (int e = 0; e < kEach; ++e) {
+      if (a0 + e < ncand) {
+        const uint32_t k = (uint32_t)(cand[a0 + e] >> 32);
+        const int64_t idx = us + (int64_t)(uint32_t)cand[a0 + e];
+        const bool in0 = idx >= w0 && idx < w1;
+        le += k <= lo;
+        lt += k < hi;
+        cb += in0 && k < lo;
+        clo += in0 && k == lo;
+        csn += in0 && k > lo && k < hi;
+      }
+    }
+    atomicAdd(&s_pa, le);
+    atomicAdd(&s_pb, lt);
+    atomicAdd(&s_cb, cb);
+    atomicAdd(&s_clo, clo);
+    atomicAdd(&s_cs, csn);
+    __syncthreads();
+    const int pa = s_pa, pb = s_pb;
+    unsigned long long keep[kEach];
+#pragma unroll
+    for (int e = 0; e < kEach; ++e) keep[e] = pa + a0 + e < pb ? cand[pa + a0 + e] : 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kEach; ++e)
+      if (pa + a0 + e < pb) cand[a0 + e] = keep[e];
+    __syncthreads();
+    ncand = pb > pa ? pb - pa : 0;
   }
   // sorted positions of the candidates outside C, ascending
   if (threadIdx.x == 0) s_nedge = 0;
