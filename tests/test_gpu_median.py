@@ -38,7 +38,7 @@ def run(ctx, x, window, tdt=torch.float32):
 @pytest.mark.parametrize("n,window", [(1, 1), (2, 3), (7, 1), (10, 7), (50, 99), (100, 101),
                                       (300, 31), (1000, 257), (5000, 1001), (20000, 4001),
                                       (3000, 5999), (70001, 4097), (200_003, 20001)])
-@pytest.mark.parametrize("kind", ["noise", "ties", "const", "ramp"])
+@pytest.mark.parametrize("kind", ["noise", "ties", "const", "ramp", "offset"])
 def test_running_median_bit_exact(ctx, n, window, kind):
     print(f"median n={n} window={window} {kind}", flush=True)
     g = np.random.default_rng(n + window)
@@ -49,6 +49,8 @@ def test_running_median_bit_exact(ctx, n, window, kind):
         x[::11] = -0.0  # equal to +0 in the order
     elif kind == "const":
         x = np.full(n, -1.5, np.float32)
+    elif kind == "offset":  # every key shares its top digit: the full three-digit selection
+        x = (100.0 + g.standard_normal(n)).astype(np.float32)
     else:
         x = np.cumsum(g.uniform(0, 1, n)).astype(np.float32)
     assert np.array_equal(run(ctx, x, window), expected(x, window))
