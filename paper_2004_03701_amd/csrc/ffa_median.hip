@@ -300,18 +300,48 @@ __global__ __launch_bounds__(kMedThreads) void k_running_median(const void* x, i
   while (np2 < ncand) np2 <<= 1;
   for (int j = ncand + threadIdx.x; j < np2; j += kMedThreads) cand[j] = ~0ull;
   __syncthreads();
-  // bitonic sort of the candidates by (key, index)
+  // bitonic sort of the candidates by (key, index); two stages per pass
+  // over LDS where the stride allows: a thread takes the four elements that
+  // the two stages of strides s and s / 2 mix among themselves
   for (int size = 2; size <= np2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < (np2 >> 1); t += kMedThreads) {
-        const int a = 2 * t - (t & (stride - 1));
-        const int b = a + stride;
-        const bool up = (a & size) == 0;
-        const unsigned long long va = cand[a], vb = cand[b];
-        if ((va > vb) == up) {
-          cand[a] = vb;
-          cand[b] = va;
+    int stride = size >> 1;
+    while (stride > 0) {
+      if (stride >= 2) {
+        const int half = stride >> 1;
+        const int lh = __builtin_ctz(half);
+        for (int g = threadIdx.x; g < (np2 >> 2); g += kMedThreads) {
+          const int base = ((g >> lh) << (lh + 2)) | (g & (half - 1));
+          const bool up = (base & size) == 0;
+          unsigned long long v0 = cand[base], v1 = cand[base + half];
+          unsigned long long v2 = cand[base + stride], v3 = cand[base + stride + half];
+          auto cx = [up](unsigned long long& a, unsigned long long& b) {
+            if ((a > b) == up) {
+              const unsigned long long t = a;
+              a = b;
+              b = t;
+            }
+          };
+          cx(v0, v2);
+          cx(v1, v3);
+          cx(v0, v1);
+          cx(v2, v3);
+          cand[base] = v0;
+          cand[base + half] = v1;
+          cand[base + stride] = v2;
+          cand[base + stride + half] = v3;
         }
+        stride >>= 2;
+      } else {
+        for (int t = threadIdx.x; t < (np2 >> 1); t += kMedThreads) {
+          const int a = 2 * t;
+          const bool up = (a & size) == 0;
+          const unsigned long long va = cand[a], vb = cand[a + 1];
+          if ((va > vb) == up) {
+            cand[a] = vb;
+            cand[a + 1] = va;
+          }
+        }
+        stride = 0;
       }
       __syncthreads();
     }
