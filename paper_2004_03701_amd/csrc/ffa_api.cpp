@@ -1254,6 +1254,8 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
                           void* stream) {
   if (!ctx) return FFA_ERR_INVALID_ARG;
   if (!series || !out_dev) return fail(ctx, FFA_ERR_INVALID_ARG, "null series or out");
+  if (reinterpret_cast<uintptr_t>(out_dev) & 15)  // outputs are stored 16 bytes at a time
+    return fail(ctx, FFA_ERR_INVALID_ARG, "out must be 16-byte aligned");
   if (nsamp < 1 || nsamp > INT32_MAX) return fail(ctx, FFA_ERR_INVALID_ARG, "nsamp out of range");
   if (dtype != FFA_F32 && dtype != FFA_BF16 && dtype != FFA_F16)
     return fail(ctx, FFA_ERR_INVALID_ARG, "unknown dtype");

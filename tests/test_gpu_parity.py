@@ -165,6 +165,15 @@ def test_downsample_storage_types_and_alignment(ctx, tdt, dt, offset, ds):
     check_downsampled(y.astype(np.float64), xn, ds_fx, oracle.downsample(xn, ds_fx, nout), ulp)
 
 
+def test_downsample_unaligned_output_is_refused(ctx):
+    n = 10_000
+    xd = dev(np.random.default_rng(2).standard_normal(n).astype(np.float32))
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    st = ffa.lib().ffa_downsample(ctx, xd.data_ptr(), n, ffa.FFA_F32, None, 1 << 32, 100,
+                                  out.data_ptr() + 4, None)
+    assert st == ffa.FFA_ERR_INVALID_ARG
+
+
 def test_downsample_factor_beyond_block_is_refused(ctx):
     # a window longer than a downsampling block can hold is an argument error
     n = 100_000
