@@ -72,6 +72,18 @@ def test_running_median_16bit_input(ctx, tdt):
     assert np.array_equal(run(ctx, x, 1001, tdt), expected(xq, 1001))
 
 
+@pytest.mark.parametrize("tdt,odt", [(torch.bfloat16, ffa.FFA_BF16), (torch.float16, ffa.FFA_F16)])
+def test_running_median_16bit_output(ctx, tdt, odt):
+    # the de-reddened series in a 16-bit storage type: the FP32 difference
+    # rounded to nearest even
+    x = np.random.default_rng(10).standard_normal(100_000).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    out = ffa.ffa_running_median(ctx, xd, 1001, out_dtype=odt)
+    torch.cuda.synchronize()
+    want = torch.from_numpy(expected(x, 1001)).to(tdt)
+    assert torch.equal(out.cpu().view(torch.int16), want.view(torch.int16))
+
+
 def test_running_median_impulse_passes_unchanged(ctx):
     # Sec. 5.2: a constant impulse narrower than half the window is left
     # intact by x - median

@@ -350,6 +350,28 @@ def test_batch_with_and_without_de_reddening(ctx):
     assert "median_ms" in tm_before
 
 
+@pytest.mark.parametrize("tdt,dt,bmax,bmed", [(torch.bfloat16, ffa.FFA_BF16, 0.1, 0.01),
+                                              (torch.float16, ffa.FFA_F16, 0.01, 1e-3)])
+def test_low_precision_search_with_de_reddening(ctx, tdt, dt, bmax, bmed):
+    # 16-bit storage with the running median: the de-reddened series and the
+    # downsampled series are kept in the storage type; against the oracle on
+    # the stored (dequantised) samples
+    g = synth.rng(22, 0)
+    n = 400_000
+    x = (synth.noise(n, g).astype(np.float64) + synth.red_noise(n, 0.3, g)).astype(np.float32)
+    xq = torch.from_numpy(x).to(tdt)
+    xdq = xq.float().numpy()
+    prm = ffa.make_params(64e-6, 0.1, 2.0, 240, 259, synth.WIDTHS_DUTY, dtype=dt,
+                          median_window=4001)
+    _, _, snr = ffa.ffa_search(ctx, xq.cuda(), prm)
+    torch.cuda.synchronize()
+    assert ffa.ffa_sync_status(ctx) == ffa.FFA_OK
+    ref = oracle.search(xdq, 64e-6, 0.1, 2.0, 240, 259, synth.WIDTHS_DUTY, median_window=4001)
+    err = np.abs(snr.cpu().numpy() - ref.snr)
+    print(f"{tdt} de-reddened: max |dS/N| {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() < bmax and np.median(err) < bmed
+
+
 def batch_inputs(n):
     xs, prms = [], []
     for i in range(n):
