@@ -239,3 +239,46 @@ def test_peak_capacity_degenerate_and_errors(ctx):
     got, counts, poly = ffa.ffa_find_peaks_batch(ctx, snr, [prm], [n], [0],
                                                  ffa.make_peak_params(min_points=10 ** 6))
     assert counts[0] == 0 and np.all(np.isnan(poly))
+
+
+def test_multi_dm_chain_on_search_output(ctx):
+    # Sec. 5.7 end to end: one pulsar seen in 8 DM trials with an S/N that
+    # peaks at the right DM; the periodograms' peaks of all trials are
+    # clustered in frequency and the clusters flagged as harmonics. The
+    # brightest cluster is the pulsar's frequency, its brightest member comes
+    # from the brightest trial, and the flags satisfy their definition on the
+    # clusters the chain produced.
+    n, tsamp = 1 << 20, 64e-6
+    T = n * tsamp
+    period_s = 0.7131
+    amps = [4.0, 8.0, 12.0, 16.0, 20.0, 16.0, 12.0, 8.0]
+    xs = []
+    for i, a in enumerate(amps):
+        g = synth.rng(23, i)
+        pu = synth.Pulse(period=period_s / tsamp, duty=0.03, amplitude=a, phi0=0.25)
+        xs.append(torch.from_numpy(synth.inject(synth.noise(n, g), pu)).cuda())
+    prm = [ffa.make_params(tsamp, 0.2, 2.0, 240, 259, synth.WIDTHS_DUTY) for _ in amps]
+    snr, offs = ffa.ffa_search_batch(ctx, xs, prm)
+    torch.cuda.synchronize()
+    peaks, counts, _ = ffa.ffa_find_peaks_batch(ctx, snr, prm, [n] * len(amps), offs)
+    assert counts.sum() > 0
+    freq = 1.0 / peaks["period"]
+    tol = 1.0 / T
+    cl, br, mb = ffa.ffa_cluster_frequencies(freq, peaks["snr"], tol)
+    cf, cs = freq[br], peaks["snr"][br]
+    top = int(np.argmax(cs))
+    assert abs(cf[top] - 1.0 / period_s) <= 2 * tol
+    assert peaks["series"][br[top]] == int(np.argmax(amps))
+    par, num, den = ffa.ffa_flag_harmonics(cf, cs, tol, 8)
+    assert par[top] == -1
+    for j in range(len(cf)):
+        if par[j] < 0:
+            continue
+        i, a, b = int(par[j]), int(num[j]), int(den[j])
+        assert cs[i] > cs[j] or (cs[i] == cs[j] and i < j)
+        assert abs(cf[j] - a / b * cf[i]) <= tol * (1 + a / b)
+    # the pulsar's harmonics that the search found are flagged against it
+    for j in range(len(cf)):
+        for a in (2, 3):
+            if j != top and abs(cf[j] - a * cf[top]) <= tol * (1 + a) and cs[j] < cs[top]:
+                assert par[j] >= 0
