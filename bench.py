@@ -425,7 +425,7 @@ def main_single(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (series shard across GPUs with no exchange: run one process per GPU on its share); --gpus must be 1"}))
         sys.exit(2)
     if a.workload == "uneven":
         return main_uneven(a)
