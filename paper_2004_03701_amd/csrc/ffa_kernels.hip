@@ -339,7 +339,7 @@ __global__ void k_norm_from_stats(const double* stats, float* norm) {
 // magnitude and with it the FP32 rounding of P.
 // ---------------------------------------------------------------------------
 
-constexpr int kDsThreads = 512;
+constexpr int kDsThreads = 1024;
 constexpr int kDsPerThread = 16;                     // samples a thread holds per round
 constexpr int kDsRound = kDsThreads * kDsPerThread;  // samples per round
 
@@ -1959,7 +1959,7 @@ hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dt
   return hipGetLastError();
 }
 
-constexpr int kDsMaxRounds = 4;  // LDS of a block: kDsMaxRounds * kDsRound floats at most
+constexpr int kDsMaxRounds = 2;  // LDS of a block: kDsMaxRounds * kDsRound floats at most
 constexpr int kDsMaxLdsBytes = (kDsMaxRounds * kDsRound + 4) * (int)sizeof(float);
 
 int32_t downsample_lds_floats(int32_t block, int32_t halo) {
