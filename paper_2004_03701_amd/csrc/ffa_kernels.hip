@@ -1586,9 +1586,10 @@ __device__ __forceinline__ void snr_segment(const float* row, int n0, int p, flo
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     float b = best[k];
+    // one chain through b: each pair of starts is one three-input max
 #pragma unroll
     for (int u = 0; u + 1 < kSnrSeg; u += 2)
-      b = fmaxf(b, fmaxf(S[u + G::kW[k]] - S[u], S[u + 1 + G::kW[k]] - S[u + 1]));
+      b = fmaxf(fmaxf(b, S[u + G::kW[k]] - S[u]), S[u + 1 + G::kW[k]] - S[u + 1]);
     best[k] = b;
   }
 }
