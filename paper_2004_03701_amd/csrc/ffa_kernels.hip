@@ -466,13 +466,18 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
       }
       if (lane == 0) s_cum[0] = 0;
     }
-    float woff = 0.0f, total = 0.0f;
-#pragma unroll
-    for (int w = 0; w < kDsThreads / 64; ++w) {
-      const float pw = s_part[r & 1][w];
-      if (w < wave) woff += pw;
-      total += pw;
-    }
+    // the waves' totals scanned across the first 16 lanes (one DPP row):
+    // the wave's offset and the round's total are then two lane reads
+    static_assert(kDsThreads / 64 == 16, "one DPP row of wave totals");
+    float pw = lane < kDsThreads / 64 ? s_part[r & 1][lane] : 0.0f;
+    pw += dpp_f32<0x111, 0xf>(pw);  // row_shr:1
+    pw += dpp_f32<0x112, 0xf>(pw);  // row_shr:2
+    pw += dpp_f32<0x114, 0xf>(pw);  // row_shr:4
+    pw += dpp_f32<0x118, 0xf>(pw);  // row_shr:8
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const float total = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pw), kDsThreads / 64 - 1));
+    const float woff =
+        wv > 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pw), wv > 0 ? wv - 1 : 0)) : 0.0f;
     const float p0 = carry + woff + (incl - run);  // P at the thread's first sample
     float4* dst = reinterpret_cast<float4*>(ps + q);
 #pragma unroll
