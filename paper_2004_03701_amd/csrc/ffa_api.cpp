@@ -535,7 +535,7 @@ ffa_status reserve_job(ffa_ctx* ctx, const Job& job) {
                          (size_t)job.scr_cells * 4 + 16,
                          (size_t)job.scr_cells * 4 + 16,
                          (size_t)job.nseries * 2 * sizeof(double),
-                         (size_t)job.nseries * 2 * sizeof(float),
+                         (size_t)job.nseries * kNormFloats * sizeof(float),
                          (size_t)job.nseries * job.stats_blocks * 2 * sizeof(double),
                          16,
                          (size_t)std::max(job.max_counters, 1) * sizeof(int32_t),
@@ -892,7 +892,7 @@ ffa_status build_na_job(ffa_ctx* ctx, const void* series, int64_t nsamp,
     nj->off_stats = o;
     o = align256(o + 2 * sizeof(double));
     nj->off_norm = o;
-    o = align256(o + 2 * sizeof(float));
+    o = align256(o + kNormFloats * sizeof(float));
     nj->off_partials = o;
     o = align256(o + (size_t)job.stats_blocks * 2 * sizeof(double));
     nj->off_dered = o;
@@ -1240,7 +1240,7 @@ ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int
   HIP_TRY(ctx, hipMemcpy(tmp.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
   const int32_t bps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(2048, nsamp / 4096));
   HIP_TRY(ctx, grow(ctx, ctx->partials, (size_t)bps * 2 * sizeof(double)), "allocate");
-  HIP_TRY(ctx, grow(ctx, ctx->norm, 2 * sizeof(float)), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->norm, kNormFloats * sizeof(float)), "allocate");
   HIP_TRY(ctx, grow(ctx, ctx->flag, 16, true), "allocate");
   HIP_TRY(ctx, launch_stats(tmp.as<SeriesDev>(), 1, dtype, bps, ctx->partials.as<double>(),
                             stats_dev, ctx->norm.as<float>(), ctx->flag.as<int32_t>(), st),
@@ -1275,7 +1275,7 @@ ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32
   HIP_TRY(ctx, t2.reserve(sizeof od), "allocate");
   HIP_TRY(ctx, hipMemcpy(t1.ptr, &sd, sizeof sd, hipMemcpyHostToDevice), "upload");
   HIP_TRY(ctx, hipMemcpy(t2.ptr, &od, sizeof od, hipMemcpyHostToDevice), "upload");
-  HIP_TRY(ctx, grow(ctx, ctx->norm, 2 * sizeof(float)), "allocate");
+  HIP_TRY(ctx, grow(ctx, ctx->norm, kNormFloats * sizeof(float)), "allocate");
   if (stats_dev)
     HIP_TRY(ctx, launch_norm_from_stats(stats_dev, ctx->norm.as<float>(), st), "norm kernel");
   const int64_t nblocks = (nsamp + bs - 1) / bs;

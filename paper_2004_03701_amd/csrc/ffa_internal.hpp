@@ -42,6 +42,10 @@ constexpr int kLdsBytes = 160 * 1024;
 // the downsampler emits kDsGroup consecutive outputs of an octave at a time,
 // with whole 16-byte stores.
 constexpr int kDsGroup = 8;
+// Normalisation record of a series for the downsampler (FP32): mean rounded
+// to FP32, 1 / std, the mean's FP32 rounding residual (mean - that float),
+// and a pad word.
+constexpr int kNormFloats = 4;
 inline __host__ __device__ int wg_lds_bytes(int waves) { return kLdsBytes / kWavesLarge * waves; }
 // LDS set aside for the S/N step; range tiles keep their pair-operation
 // records of kOpInts ints here during the merges, so a range tile has at most

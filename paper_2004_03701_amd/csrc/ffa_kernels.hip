@@ -309,8 +309,11 @@ __global__ __launch_bounds__(64) void k_stats_final(const SeriesDev* series, int
     const double sd_ = sqrt(var);
     stats[2 * blockIdx.x] = mean;
     stats[2 * blockIdx.x + 1] = sd_;
-    norm[2 * blockIdx.x] = (float)mean;
-    norm[2 * blockIdx.x + 1] = (float)(1.0 / sd_);
+    float* nr = norm + kNormFloats * blockIdx.x;
+    nr[0] = (float)mean;
+    nr[1] = (float)(1.0 / sd_);
+    nr[2] = (float)(mean - (double)(float)mean);
+    nr[3] = 0.0f;
     if (sd.normalise && !(sd_ > 0.0 && isfinite(sd_) && isfinite(mean))) atomicOr(flag, 1);
   }
 }
@@ -320,6 +323,8 @@ __global__ void k_clear_flag(int32_t* flag) { *flag = 0; }
 __global__ void k_norm_from_stats(const double* stats, float* norm) {
   norm[0] = (float)stats[0];
   norm[1] = (float)(1.0 / stats[1]);
+  norm[2] = (float)(stats[0] - (double)(float)stats[0]);
+  norm[3] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -399,6 +404,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   __shared__ uint64_t s_dsfx[kDsMaxOctaves];
   __shared__ int64_t s_off[kDsMaxOctaves];
   __shared__ int s_cum[kDsMaxOctaves + 1];
+  __shared__ float s_ncorr[kDsMaxOctaves];
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
   const int si = block_series ? block_series[blockIdx.x] : 0;
@@ -409,8 +415,12 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
   const int64_t cend = min(sd.nsamp, c1 + (int64_t)sd.halo);
   const int len = (int)(cend - c0);
   const int rounds = (len + kDsRound - 1) / kDsRound;
-  const float mean = sd.normalise ? norm[2 * si] : 0.0f;
-  const float inv = sd.normalise ? norm[2 * si + 1] : 1.0f;
+  // the samples minus the FP32 mean are summed; the window sums then drop
+  // the mean's FP32 residual times the window length (ds), so that a large
+  // mean leaves no bias that grows with the window
+  const float mean = sd.normalise ? norm[kNormFloats * si] : 0.0f;
+  const float inv = sd.normalise ? norm[kNormFloats * si + 1] : 1.0f;
+  const float mean_lo = sd.normalise ? norm[kNormFloats * si + 2] : 0.0f;
   const int esize = DT == FFA_F32 ? 4 : 2;
   const void* base = static_cast<const unsigned char*>(sd.ptr) + c0 * esize;
   // block starts are multiples of 8 samples: the 16-byte loads line up when
@@ -435,6 +445,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     s_j1[tid] = j1;
     s_dsfx[tid] = o.ds_fx;
     s_off[tid] = o.off;
+    s_ncorr[tid] = (float)(-(double)mean_lo * ((double)o.ds_fx * 0x1p-32) * (double)inv);
     // groups, scanned below
     s_cum[tid + 1] = j1 > j0 ? (int)((j1 - 1) / kDsGroup - j0 / kDsGroup + 1) : 0;
   }
@@ -501,6 +512,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
     for (int step = kDsMaxOctaves / 2; step >= 1; step >>= 1)
       if (k + step < noct && s_cum[k + step] <= u) k += step;
     const uint64_t dsfx = s_dsfx[k];
+    const float ncorr = s_ncorr[k];
     const int64_t jlo = s_j0[k], jhi = s_j1[k];
     const int64_t jg = (jlo / kDsGroup + (u - s_cum[k])) * kDsGroup;  // first output of the group
     // edges e = 0..kDsGroup at a = (jg + e) ds, in 2^-32 samples from the
@@ -521,7 +533,7 @@ __global__ __launch_bounds__(kDsThreads) void k_downsample(const SeriesDev* seri
       // window [a_e-1, a_e): the part of the first sample right of its edge,
       // the whole samples between, and the part of the last sample left of
       // its edge
-      if (e > 0) y[e - 1] = ((d_prev - g_prev) + (p0 - p1_prev) + g) * inv;
+      if (e > 0) y[e - 1] = fmaf((d_prev - g_prev) + (p0 - p1_prev) + g, inv, ncorr);
       d_prev = d;
       g_prev = g;
       p1_prev = p1;

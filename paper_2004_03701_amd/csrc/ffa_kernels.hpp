@@ -32,7 +32,8 @@ struct OctaveDev {
 
 // Normalisation statistics of each series (Sec. 5.2), FP64:
 // stats[2i] = mean, stats[2i+1] = population standard deviation.
-// norm[2i] = mean, norm[2i+1] = 1 / std as FP32 for the downsampler.
+// norm[kNormFloats i ..] = FP32 mean, 1 / std, the mean's FP32 residual and a
+// pad word, for the downsampler.
 // partials holds blocks_per_series * nseries * 2 doubles. flag |= 1 when a
 // normalised series has zero or non-finite variance.
 hipError_t launch_stats(const SeriesDev* series_dev, int32_t nseries, int32_t dtype,

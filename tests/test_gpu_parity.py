@@ -129,7 +129,7 @@ def check_downsampled(y, xn, ds_fx, ref, out_ulp):
     assert np.sqrt(np.mean(err ** 2)) <= rms_allow
 
 
-@pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3, 5000.3])
+@pytest.mark.parametrize("ds", [1.0, 3.0, 1.37, 32.552083333333336, 651.04, 2000.3, 5000.3, 16000.3])
 def test_downsample(ctx, ds):
     n = 300_001
     x = (np.random.default_rng(5).standard_normal(n) + 0.3).astype(np.float32)
@@ -139,6 +139,25 @@ def test_downsample(ctx, ds):
     st = ffa.ffa_series_stats(ctx, xd)
     y = ffa.ffa_downsample(ctx, xd, ds_fx, nout, stats=st).cpu().numpy().astype(np.float64)
     mu, sd = oracle.normalise_stats(x)
+    xn = (x.astype(np.float64) - mu) / sd
+    check_downsampled(y, xn, ds_fx, oracle.downsample(xn, ds_fx, nout), 0.0)
+
+
+@pytest.mark.parametrize("ds", [651.04, 5000.3, 16000.3])
+def test_downsample_large_mean(ctx, ds):
+    # a series far from zero mean: the FP32 mean the samples are shifted by
+    # is off by up to half its ulp, which would bias every window by that
+    # times its length; the kernel drops the residual per window, so the
+    # outputs meet the same bound as a zero-mean series
+    n = 300_001
+    x = (1000.0 + np.random.default_rng(6).standard_normal(n)).astype(np.float32)
+    ds_fx = int(math.floor(ds * 2 ** 32 + 0.5))
+    nout = (n << 32) // ds_fx
+    xd = dev(x)
+    st = ffa.ffa_series_stats(ctx, xd)
+    y = ffa.ffa_downsample(ctx, xd, ds_fx, nout, stats=st).cpu().numpy().astype(np.float64)
+    mu, sd = oracle.normalise_stats(x)
+    assert abs(float(np.float32(mu)) - mu) * ds / sd > 1e-3  # the residual the kernel corrects
     xn = (x.astype(np.float64) - mu) / sd
     check_downsampled(y, xn, ds_fx, oracle.downsample(xn, ds_fx, nout), 0.0)
 
@@ -181,6 +200,23 @@ def test_downsample_factor_beyond_block_is_refused(ctx):
     ds_fx = 20_000 << 32
     with pytest.raises(RuntimeError):
         ffa.ffa_downsample(ctx, xd, ds_fx, n // 20_000)
+
+
+def test_downsample_widest_window_boundary(ctx):
+    # the halo, floor(ds) + 2 samples padded to 8, and the block must fill at
+    # most two LDS rounds of 16,384 samples with the block at least as long as
+    # the halo: ds = 16,381 is the widest whole factor accepted, and its
+    # outputs still match the oracle; 16,383 is refused
+    n = 200_000
+    x = np.random.default_rng(4).standard_normal(n).astype(np.float32)
+    xd = dev(x)
+    ds_fx = 16_381 << 32
+    nout = (n << 32) // ds_fx
+    y = ffa.ffa_downsample(ctx, xd, ds_fx, nout).cpu().numpy().astype(np.float64)
+    xn = x.astype(np.float64)
+    check_downsampled(y, xn, ds_fx, oracle.downsample(xn, ds_fx, nout), 0.0)
+    with pytest.raises(RuntimeError):
+        ffa.ffa_downsample(ctx, xd, 16_383 << 32, n // 16_383)
 
 
 # ---------------------------------------------------------------------------
