@@ -211,8 +211,8 @@ ffa_status ffa_series_stats(ffa_ctx* ctx, const void* series, int64_t nsamp, int
  * normalisation is applied, else (x - mean) / std with stats_dev as written by
  * ffa_series_stats. out_dev (DEVICE, 16-byte aligned) receives nout samples
  * of `dtype`; nout <= floor(nsamp * 2^32 / ds_fx), ds_fx >= 2^32, and the
- * widest window, ds_fx / 2^32 samples, must leave a downsampling block room
- * (about 16,000 samples at most). FFA_ERR_INVALID_ARG otherwise. */
+ * window must leave a downsampling block room: floor(ds_fx / 2^32) <= 16,382.
+ * FFA_ERR_INVALID_ARG otherwise. */
 ffa_status ffa_downsample(ffa_ctx* ctx, const void* series, int64_t nsamp, int32_t dtype,
                           const double* stats_dev, uint64_t ds_fx, int64_t nout, void* out_dev,
                           void* stream);

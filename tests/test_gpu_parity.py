@@ -205,12 +205,12 @@ def test_downsample_factor_beyond_block_is_refused(ctx):
 def test_downsample_widest_window_boundary(ctx):
     # the halo, floor(ds) + 2 samples padded to 8, and the block must fill at
     # most two LDS rounds of 16,384 samples with the block at least as long as
-    # the halo: ds = 16,381 is the widest whole factor accepted, and its
-    # outputs still match the oracle; 16,383 is refused
+    # the halo: floor(ds) = 16,382 is the widest accepted, and its outputs
+    # still match the oracle; 16,383 is refused
     n = 200_000
     x = np.random.default_rng(4).standard_normal(n).astype(np.float32)
     xd = dev(x)
-    ds_fx = 16_381 << 32
+    ds_fx = (16_382 << 32) + (1 << 31)
     nout = (n << 32) // ds_fx
     y = ffa.ffa_downsample(ctx, xd, ds_fx, nout).cpu().numpy().astype(np.float64)
     xn = x.astype(np.float64)
