@@ -119,6 +119,9 @@ ffa_status ffa_plan_export(const ffa_search_params* params, int64_t nsamp, doubl
                            uint64_t* ds_fx, int64_t capacity);
 
 /* Periodogram of one series (Sec. 5.3 - 5.5).
+ * The widest downsampling window of the plan (the last pseudo-octave's
+ * factor, about period_max / (bins_min tsamp)) must satisfy floor(ds) <=
+ * 16,382, as for ffa_downsample; FFA_ERR_INVALID_ARG otherwise.
  *   series       DEVICE, nsamp samples of params->dtype.
  *   period_host  HOST, capacity_rows doubles or NULL: trial period of each row.
  *   bins_host    HOST, capacity_rows int32 or NULL: bins p of each row.

@@ -320,6 +320,20 @@ def test_invalid_arguments_do_no_device_work(ctx):
     assert (snr == 0).all()
 
 
+def test_search_window_wider_than_a_downsampling_block_is_refused(ctx):
+    # the first factor P_min / (b_min tau) = 16,500 already leaves no room for a
+    # downsampling block (floor(ds) <= 16,382): an argument error, no device work
+    x = dev(np.zeros(1 << 23, np.float32))
+    prm = ffa.make_params(1.0, 240 * 16_500.0, 5.0e6, 240, 259, (1, 2))
+    assert ffa.ffa_plan_rows(prm, 1 << 23) > 0
+    snr = torch.zeros((ffa.ffa_plan_rows(prm, 1 << 23), 2), device="cuda")
+    with pytest.raises(ffa.FFAError) as e:
+        ffa.ffa_search(ctx, x, prm, snr=snr)
+    assert e.value.status == ffa.FFA_ERR_INVALID_ARG
+    assert "downsampling block" in ffa.ffa_last_error(ctx)
+    assert (snr == 0).all()
+
+
 def test_search_duty_width_grid(ctx):
     g = synth.rng(9, 0)
     x = synth.inject(synth.noise(1 << 21, g),
